@@ -1,0 +1,239 @@
+/*
+ * pfeig — polynomial-filtered interior eigensolver for the mass-weighted
+ * Hessian of a 3N-dimensional vibrational problem, on one AMD MI355X (gfx950).
+ *
+ * Method: Accaputo, Derlet, Arbenz, "Solving large-scale interior eigenvalue
+ * problems to investigate the vibrational properties of the boson peak regime
+ * in amorphous materials" (2019).  The calls follow the paper's BosonPeak
+ * pipeline (Algorithm 3): import H (step 2), Lanczos bounds (step 3), spectral
+ * map (step 4, eq. transf.1), filter design (step 6, Sec. 2.6), eigenpairs in
+ * [lam_lo, lam_hi] with small residuals (step 7, Algorithm 4 with
+ * Rayleigh-Ritz, Algorithm 1), plus the filter application itself
+ * (Algorithm 2), its reverse-mode adjoint, and the eigenvalue count (Sec. 2.4).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Matrices are 3x3 block-CSR over atoms: row_ptr[n_atoms+1] (int64),
+ *   col_idx[nnzb] (int32, strictly increasing within a row, the diagonal block
+ *   present in every row), values [nnzb][3][3] row-major FP64.  n = 3 n_atoms.
+ * - Multivectors are row-major [n][ld]: the q columns of one matrix row are
+ *   contiguous, row r starts at r*ld.  Vector i of an eigenvector output is
+ *   contiguous instead ([nev][n]).
+ * - Pointers are host memory unless the call's flags contain PFE_DEVICE_PTRS,
+ *   in which case they are device memory of the handle's device.  The caller
+ *   owns every pointer it passes; the library copies what it keeps.  Device
+ *   inputs are read stream-ordered on the handle's stream and must stay valid
+ *   until the call returns (every call synchronises its stream before
+ *   returning, except where stated).
+ * - Errors are returned as pfe_status, never thrown; pfe_last_error gives a
+ *   message.  A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef PFEIG_H
+#define PFEIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pfe_ctx* pfe_handle;
+
+typedef enum {
+  PFE_OK = 0,
+  PFE_EINVAL = -1,      /* bad argument, NaN/Inf, unsorted columns, mass <= 0 */
+  PFE_ENOTSYM = -2,     /* a stored block K_ij differs from K_ji^T, or K_ji missing */
+  PFE_ENOMEM = -3,      /* device allocation failed */
+  PFE_EHIP = -4,        /* HIP runtime error */
+  PFE_ENOCONV = -5,     /* max_iter reached; partial results are returned */
+  PFE_ECAPACITY = -6,   /* more eigenvalues in the window than nev */
+  PFE_EBOUNDS = -7,     /* filter iterates grew: the spectrum exceeds [lam_lb, lam_ub] */
+  PFE_ESTATE = -8,      /* call out of order (no Hessian, no bounds) */
+  PFE_EBREAKDOWN = -9   /* orthonormalisation broke down even with a shift */
+} pfe_status;
+
+/* flags */
+#define PFE_DEVICE_PTRS 1u   /* array arguments are device pointers */
+#define PFE_BLOCKS_ARE_H 2u  /* set_hessian: blocks are already mass-weighted H */
+
+/* smoothing of the Chebyshev coefficients (Sec. 2.3) */
+#define PFE_SMOOTH_NONE 0
+#define PFE_SMOOTH_JACKSON 1   /* eq. jackson_smoothing */
+#define PFE_SMOOTH_LANCZOS 2   /* eq. lanczos_smoothing (sigma damping) */
+
+/* arithmetic of the filter */
+#define PFE_FP64 0
+#define PFE_FP32 1   /* FP32 block values and vectors, FP32 accumulation */
+
+/* Create a handle on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * run on (NULL: the library creates its own stream).  The stream must have the
+ * default priority. */
+pfe_status pfe_create(int device, void* hip_stream, pfe_handle* out);
+void pfe_destroy(pfe_handle h);
+/* Message describing the last non-OK status of this handle ("" if none). */
+const char* pfe_last_error(pfe_handle h);
+/* Library version string. */
+const char* pfe_version(void);
+
+/* ---------------------------------------------------------------- Hessian
+ * Import the Hessian (Algorithm 3, step 2) and form H_ij = K_ij/sqrt(m_i m_j)
+ * on the device (Sec. 1, eq. intro.2) unless PFE_BLOCKS_ARE_H.  Validates:
+ * sorted columns with the diagonal present (EINVAL), finite values and masses
+ * > 0 (EINVAL), every block's transpose partner present and equal to its
+ * transpose (ENOTSYM).  Replaces any previous Hessian and clears the bounds.
+ * `masses` may be NULL only with PFE_BLOCKS_ARE_H (the spring gradient call
+ * then needs them and fails with ESTATE). */
+pfe_status pfe_set_hessian(pfe_handle h, int64_t n_atoms, int64_t nnzb,
+                           const int64_t* row_ptr, const int32_t* col_idx,
+                           const double* blocks, const double* masses, uint32_t flags);
+
+/* ----------------------------------------------------------------- bounds
+ * `steps` Lanczos steps with full re-orthogonalisation on H (Algorithm 3,
+ * step 3) from start vector v0 (length n; NULL: a seeded Gaussian vector from
+ * the library's own counter-based generator).  Returns theta_max (largest Ritz
+ * value), lam_ub = theta_max + |beta_m s_m| (Ritz residual bound) and
+ * lam_lb = 0 (H is positive semi-definite by construction), and stores
+ * (lam_lb, lam_ub) in the handle for the spectral map. */
+pfe_status pfe_estimate_bounds(pfe_handle h, int32_t steps, const double* v0, uint64_t seed,
+                               uint32_t flags, double* lam_lb, double* lam_ub, double* theta_max);
+/* Store explicit bounds [lam_lb, lam_ub] of the spectrum (lam_lb < lam_ub). */
+pfe_status pfe_set_bounds(pfe_handle h, double lam_lb, double lam_ub);
+
+/* ---------------------------------------------------------------- filters */
+typedef struct {
+  int32_t degree;     /* d >= 1; 0: smallest d satisfying eq. thresh at eps */
+  double eps;         /* margin in mapped units; 0: smallest eps (geometric grid,
+                         factor 1.01 from (eta-xi)/1000) satisfying eq. thresh at d */
+  double r;           /* rate of eq. thresh; 0 -> 0.1^(1/4) */
+  int32_t smoothing;  /* PFE_SMOOTH_* */
+} pfe_filter_opts;
+
+typedef struct {
+  int32_t degree;      /* d */
+  int32_t smoothing;
+  double c, e;         /* H_hat = (H - c I)/e  (eq. transf.1; e is the paper's half-width d) */
+  double xi, eta, eps; /* mapped window [xi, eta] and margin */
+  const double* coef;  /* d+1 host coefficients g_j gamma_j (eq. rho_k_smoothened); caller-owned */
+} pfe_filter;
+
+/* Host-only, pure: design the piecewise-quadratic filter pi_d of Sec. 2.6
+ * for [lam_lo, lam_hi] within bounds [lam_lb, lam_ub]: c, e of eq. transf.1,
+ * coefficients by the exact integrals of Appendix A with each piece clipped to
+ * [-1, 1], damping factors, degree or margin by eq. thresh (a margin end
+ * outside [-1, 1] constrains nothing and is dropped from the test).  Writes
+ * d+1 coefficients to coef_out (capacity coef_cap; ECAPACITY if too small)
+ * and sets out->coef = coef_out. */
+pfe_status pfe_design_filter(double lam_lo, double lam_hi, double lam_lb, double lam_ub,
+                             const pfe_filter_opts* opts, double* coef_out, int32_t coef_cap,
+                             pfe_filter* out);
+
+/* Y = pi(H_hat) X for nvec columns (Algorithm 2), X and Y row-major [n][ld].
+ * precision PFE_FP64: double arrays, H in FP64 with c and e applied as FP64
+ * scalars.  PFE_FP32: float arrays; H_hat is formed in FP64 and rounded to
+ * FP32 (cached per (c, e)), the recurrence runs in FP32.  X and Y must not
+ * overlap. */
+pfe_status pfe_apply_filter(pfe_handle h, const pfe_filter* f, int32_t nvec, const void* X,
+                            void* Y, int64_t ld, int32_t precision, uint32_t flags);
+
+/* Reverse mode of pfe_apply_filter (FP64): given X and dY = dL/dY ([n][ld]),
+ * returns dX = dL/dX ([n][ld]) and dblocks = dL/dH on every stored block
+ * ([nnzb][3][3], each stored block an independent parameter, c and e held
+ * constant), by the adjoint recurrence a_k = g_k dY + 2 H_hat a_{k+1} - a_{k+2},
+ * with the forward recurrence vectors recomputed from checkpoints kept every
+ * ckpt_stride steps (0: ceil(sqrt(d))). */
+pfe_status pfe_apply_filter_adjoint(pfe_handle h, const pfe_filter* f, int32_t nvec,
+                                    const double* X, const double* dY, double* dX,
+                                    double* dblocks, int64_t ld, int32_t ckpt_stride,
+                                    uint32_t flags);
+
+/* dblocks[b] = sum_s w_s v_s[i] v_s[j]^T on every stored block b = (i, j):
+ * the Hellmann-Feynman gradient dL/dH of L = sum_s w_s lambda_s for unit
+ * eigenvectors V ([nvec][n], vector s contiguous).  w == NULL: all ones. */
+pfe_status pfe_eigvec_block_gradient(pfe_handle h, int32_t nvec, const double* V, const double* w,
+                                     double* dblocks, uint32_t flags);
+
+/* Chain rule through H_ij = K_ij / sqrt(m_i m_j) for a spring network with
+ * K_ij = K_ji = -k u u^T, K_ii = -sum_j K_ij: from dblocks = dL/dH ([nnzb][3][3])
+ * to dk[P] (springs given as pairs[P][2] int64 (i != j) and unit vectors
+ * unit[P][3]) and dm[n_atoms]:
+ *   dk = <u u^T, G_ii/m_i + G_jj/m_j - (G_ij + G_ji)/sqrt(m_i m_j)>,
+ *   dm_i = -(1/(2 m_i)) [sum_j <G_ij, H_ij> + sum_j <G_ji, H_ji>].
+ * Needs the masses given to set_hessian. */
+pfe_status pfe_spring_gradient(pfe_handle h, int64_t n_springs, const int64_t* pairs,
+                               const double* unit, const double* dblocks, double* dk, double* dm,
+                               uint32_t flags);
+
+/* ------------------------------------------------------------------ solve */
+typedef struct {
+  int32_t block;       /* q: subspace width (1..256); should exceed the number of
+                          eigenvalues in [xi - eps, eta + eps] (Sec. 2.6) */
+  int32_t degree;      /* filter degree (0: by eq. thresh from eps) */
+  double eps;          /* filter margin in mapped units (0: by eq. thresh at degree) */
+  double r;            /* eq. thresh rate; 0 -> 0.1^(1/4) */
+  int32_t smoothing;   /* PFE_SMOOTH_* */
+  double tol;          /* residual ||H v - lambda v|| / lam_ub; 0 -> 1e-10 */
+  int32_t max_iter;    /* outer iterations (filter applications); 0 -> 100 */
+  int32_t precision;   /* PFE_FP64, or PFE_FP32: FP32 filter with FP64
+                          orthonormalisation, Rayleigh-Ritz and residuals, then
+                          exactly one FP64 refinement sweep */
+  uint64_t seed;       /* start block seed when x0 == NULL */
+  const double* x0;    /* optional start block [n][block] (host, or device with
+                          PFE_DEVICE_PTRS in flags) */
+  uint32_t flags;      /* PFE_DEVICE_PTRS applies to x0 and evecs */
+} pfe_solve_opts;
+
+typedef struct {
+  int32_t iterations;        /* outer iterations in total */
+  int32_t fp64_iterations;   /* of which with the FP64 filter */
+  int32_t refined;           /* 1 if the FP64 refinement sweep ran (FP32 form) */
+  int32_t degree;
+  double eps, c, e, xi, eta;
+  int64_t filter_steps;      /* fused Chebyshev step launches */
+  double filter_bytes;       /* algorithmic HBM bytes of those steps */
+  double t_total;            /* seconds, solve call */
+  double t_filter;           /* seconds in filter steps (events on the stream) */
+  double t_orth;             /* CholQR2 */
+  double t_rr;               /* Rayleigh-Ritz incl. H X and the small eigensolve */
+  double t_resid;            /* residuals and selection */
+  double gemm_flops;         /* Gram + projection flops */
+  double max_resid;          /* largest returned residual */
+  int32_t n_window;          /* in-window Ritz values at the end */
+} pfe_solve_stats;
+
+/* Fill opts with defaults (block 0 must then be set by the caller). */
+void pfe_solve_opts_default(pfe_solve_opts* opts);
+
+/* Eigenpairs of H with eigenvalue in the closed window [lam_lo, lam_hi]
+ * (eq. intro.33) by filtered subspace iteration (Algorithm 4 with the filter
+ * pi(H_hat) of Sec. 2.6, CholQR2 orthonormalisation and Rayleigh-Ritz on H,
+ * Algorithm 1).  Needs bounds (pfe_estimate_bounds or pfe_set_bounds).
+ * Outputs: *n_found pairs, evals[nev] ascending (host), evecs [nev][n]
+ * (unit 2-norm, largest-magnitude entry positive; host, or device with
+ * PFE_DEVICE_PTRS in opts->flags; may be NULL), resid[nev] =
+ * ||H v - lambda v|| / lam_ub (host, may be NULL), stats (may be NULL).
+ * Stops when every Ritz value within 1e-6 lam_ub of the window has a
+ * residual <= tol in two consecutive iterations with the same in-window
+ * count.  ECAPACITY: *n_found = number of in-window Ritz values (> nev),
+ * nothing else written.  ENOCONV: the converged in-window pairs are
+ * returned. */
+pfe_status pfe_solve_interval(pfe_handle h, double lam_lo, double lam_hi, int32_t nev,
+                              const pfe_solve_opts* opts, int32_t* n_found, double* evals,
+                              double* evecs, double* resid, pfe_solve_stats* stats);
+
+/* Stochastic estimate of the number of eigenvalues in [lam_lo, lam_hi]
+ * (Sec. 2.4, eq. eigval_count_estimator): (n/M) sum_l v_l^T psi(H_hat) v_l
+ * with M = nsamples unit Gaussian vectors (V [n][M] row-major if given, else
+ * drawn by the library) and psi the damped Chebyshev series of the
+ * characteristic function of the mapped window, degree `degree`. */
+pfe_status pfe_estimate_count(pfe_handle h, double lam_lo, double lam_hi, int32_t degree,
+                              int32_t smoothing, int32_t nsamples, const double* V,
+                              uint64_t seed, uint32_t flags, double* count);
+
+/* Device memory held by the handle, in bytes (Hessian copies and workspaces). */
+int64_t pfe_device_bytes(pfe_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFEIG_H */

@@ -1,0 +1,1086 @@
+// C-ABI of libpfeig and its host driver: Hessian import and validation,
+// Lanczos bounds, filter application (forward and reverse), filtered
+// subspace iteration with CholQR2 and Rayleigh-Ritz, eigenvalue count,
+// gradient chain rule.  Every numerical step runs in the library's HIP
+// kernels; the host only sequences launches, designs the filter (O(d)
+// scalars) and takes the convergence decisions from q Ritz values and
+// residuals copied back per outer iteration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using pfe::DevBuf;
+using pfe::Err;
+
+struct pfe_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // Hessian
+  int64_t n_atoms = 0, nnzb = 0;
+  bool has_h = false, has_masses = false;
+  DevBuf row_ptr, col_idx, H, transpose, masses, H32;
+  double h32_c = NAN, h32_e = NAN;
+  // bounds
+  bool has_bounds = false;
+  double lam_lb = 0, lam_ub = 0;
+  // workspaces kept between calls
+  DevBuf flags;                 // int[4] + double[4]
+  DevBuf wsA, wsB, wsC, wsD;    // multivectors
+  DevBuf wsSmall;               // q x q matrices, vectors
+  DevBuf wsRed;                 // reduction partials
+  DevBuf wsOut;                 // eigenvector output staging
+  DevBuf wsCk;                  // adjoint checkpoints
+  hipEvent_t ev[2] = {nullptr, nullptr};
+
+  pfe::Bsr bsr() const {
+    pfe::Bsr a;
+    a.n_atoms = n_atoms;
+    a.nnzb = nnzb;
+    a.row_ptr = row_ptr.as<int64_t>();
+    a.col_idx = col_idx.as<int32_t>();
+    return a;
+  }
+  int64_t n() const { return 3 * n_atoms; }
+};
+
+namespace {
+
+pfe_status finish(pfe_handle h, const Err& e) {
+  if (h) h->err = e.st == PFE_OK ? std::string() : e.msg;
+  return e.st;
+}
+
+Err select_device(pfe_handle h) {
+  PFE_HIP(hipSetDevice(h->device));
+  return pfe::ok();
+}
+
+// Copies n elements between host/device according to `device_ptrs`.
+template <typename T>
+Err upload(pfe_handle h, T* dst, const T* src, int64_t count, bool device_ptrs) {
+  if (count == 0) return pfe::ok();
+  PFE_HIP(hipMemcpyAsync(dst, src, count * sizeof(T),
+                         device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         h->stream));
+  return pfe::ok();
+}
+template <typename T>
+Err download(pfe_handle h, T* dst, const T* src, int64_t count, bool device_ptrs) {
+  if (count == 0) return pfe::ok();
+  PFE_HIP(hipMemcpyAsync(dst, src, count * sizeof(T),
+                         device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         h->stream));
+  return pfe::ok();
+}
+Err sync(pfe_handle h) {
+  PFE_HIP(hipStreamSynchronize(h->stream));
+  return pfe::ok();
+}
+
+int64_t round_up(int64_t v, int64_t m) { return ((v + m - 1) / m) * m; }
+
+// Algorithmic HBM bytes of one fused Chebyshev step: matrix values and column
+// indices once, row pointers once, and five multivector streams (T_in once,
+// T_prev read, T_out written, Y read and written).
+double step_bytes(int64_t n_atoms, int64_t nnzb, int q, int elem) {
+  return (double)nnzb * (9.0 * elem + 4.0) + 8.0 * (n_atoms + 1) + 5.0 * 3.0 * n_atoms * q * elem;
+}
+
+struct Timer {
+  hipEvent_t a, b;
+  hipStream_t s;
+  double* acc;
+  bool on;
+  Timer(pfe_handle h, double* acc_) : a(h->ev[0]), b(h->ev[1]), s(h->stream), acc(acc_), on(acc_ != nullptr) {
+    if (on) (void)hipEventRecord(a, s);
+  }
+  void stop() {
+    if (!on) return;
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, b);
+    *acc += ms * 1e-3;
+    on = false;
+  }
+  ~Timer() { stop(); }
+};
+
+// ---------------------------------------------------------------- filter
+// Y = p(A) X by Algorithm 2 with the fused step.  step 1: t1 = a1 (H t0) + b1 t0,
+// steps k >= 2: t_k = a2 (H t_{k-1}) + b2 t_{k-1} - t_{k-2}.  With clobber the
+// caller's X is overwritten (t_2 goes there) and T2 is not needed.
+template <typename T>
+Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& coef, double a1,
+               double b1, double a2, double b2, T* X, bool clobber, T* Y, T* T1, T* T2, int q,
+               int64_t ld, int64_t* steps) {
+  const pfe::Bsr A = h->bsr();
+  auto step = [&](const T* tin, const T* prev, T* out, T* y, double al, double be, double de,
+                  double yk, double go, double gi) -> hipError_t {
+    if constexpr (sizeof(T) == 8)
+      return pfe::cheb_step_f64(A, (const double*)vals, (const double*)tin, (const double*)prev,
+                                (double*)out, (double*)y, q, ld, al, be, de, yk, go, gi,
+                                h->stream);
+    else
+      return pfe::cheb_step_f32(A, (const float*)vals, (const float*)tin, (const float*)prev,
+                                (float*)out, (float*)y, q, ld, (float)al, (float)be, (float)de,
+                                (float)yk, (float)go, (float)gi, h->stream);
+  };
+  const int d = (int)coef.size() - 1;
+  if (d == 0) {
+    PFE_HIP(step(X, nullptr, T1, Y, 0.0, 0.0, 0.0, 0.0, 0.0, coef[0]));
+    if (steps) *steps += 1;
+    return pfe::ok();
+  }
+  PFE_HIP(step(X, nullptr, T1, Y, a1, b1, 0.0, 0.0, coef[1], coef[0]));
+  T* prev = X;
+  T* cur = T1;
+  for (int k = 2; k <= d; ++k) {
+    T* out = (k == 2) ? (clobber ? X : T2) : prev;
+    PFE_HIP(step(cur, prev, out, Y, a2, b2, -1.0, 1.0, coef[k], 0.0));
+    prev = cur;
+    cur = out;
+  }
+  if (steps) *steps += d;
+  return pfe::ok();
+}
+
+Err ensure_h32(pfe_handle h, double c, double e) {
+  if (h->H32.p && h->h32_c == c && h->h32_e == e) return pfe::ok();
+  PFE_HIP(h->H32.ensure((size_t)(h->nnzb + pfe::kBsrPad) * 9 * sizeof(float)));
+  PFE_HIP(pfe::zero_f32(h->H32.as<float>(), (h->nnzb + pfe::kBsrPad) * 9, h->stream));
+  PFE_HIP(pfe::shift_scale_to_f32(h->bsr(), h->H.as<double>(), c, e, h->H32.as<float>(),
+                                  h->stream));
+  h->h32_c = c;
+  h->h32_e = e;
+  return pfe::ok();
+}
+
+Err check_filter(pfe_handle h, const pfe_filter* f) {
+  if (!f || f->degree < 0 || !f->coef || !(f->e > 0) || !std::isfinite(f->c))
+    return pfe::fail(PFE_EINVAL, "invalid filter (degree, coef, c, e)");
+  if (!h->has_h) return pfe::fail(PFE_ESTATE, "no Hessian set");
+  return pfe::ok();
+}
+
+// ------------------------------------------------------ small workspaces
+struct Small {
+  double* G;       // q*q
+  double* Rinv;    // 2 q*q
+  double* S;       // q*q
+  double* Q;       // q*q
+  double* jw;      // 2 q*q
+  double* theta;   // q
+  double* res;     // q
+  double* dmax;    // 4
+  int* info;       // 4
+  int* sel;        // q
+};
+
+Err alloc_small(pfe_handle h, int q, Small* s) {
+  const size_t qq = (size_t)q * q;
+  const size_t doubles = qq * 7 + 2 * (size_t)q + 4;
+  const size_t bytes = doubles * sizeof(double) + 8 * sizeof(int) + (size_t)q * sizeof(int) + 256;
+  PFE_HIP(h->wsSmall.ensure(bytes));
+  double* p = h->wsSmall.as<double>();
+  s->G = p;
+  s->Rinv = s->G + qq;
+  s->S = s->Rinv + 2 * qq;
+  s->Q = s->S + qq;
+  s->jw = s->Q + qq;
+  s->theta = s->jw + 2 * qq;
+  s->res = s->theta + q;
+  s->dmax = s->res + q;
+  s->info = reinterpret_cast<int*>(s->dmax + 4);
+  s->sel = s->info + 8;
+  return pfe::ok();
+}
+
+Err ensure_red(pfe_handle h, int64_t n, int q) {
+  size_t need = std::max(pfe::gram_work_bytes(n, q, q), pfe::colnorm_work_bytes(n, q));
+  need = std::max(need, (size_t)q * 64 * 24 + 1024);
+  PFE_HIP(h->wsRed.ensure(need));
+  return pfe::ok();
+}
+
+// CholQR2 of X [n][ld] (q columns) in place.  If a factorisation breaks
+// down, one shifted pass (shift 11 (n q + q (q + 1)) u tr(G) bound, the
+// shifted CholeskyQR of Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa)
+// is inserted and followed by the two plain passes.  On the first pass the
+// largest squared column norm is compared with `norm_bound`^2 (EBOUNDS).
+Err cholqr2(pfe_handle h, const Small& sm, double* X, int64_t n, int q, int64_t ld,
+            double norm_bound) {
+  int passes = 2;
+  bool shifted_done = false;
+  for (int pass = 0; pass < passes; ++pass) {
+    PFE_HIP(pfe::gram_f64(n, q, q, X, ld, X, ld, sm.G, h->wsRed.p, h->stream));
+    PFE_HIP(pfe::chol_inv_f64(q, sm.G, 0.0, sm.Rinv, sm.info, sm.dmax, h->stream));
+    int info = 0;
+    double dmax = 0;
+    PFE_HIP(hipMemcpyAsync(&info, sm.info, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    PFE_HIP(hipMemcpyAsync(&dmax, sm.dmax, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    PFE_TRY(sync(h));
+    if (pass == 0 && norm_bound > 0 && !(dmax <= norm_bound * norm_bound))
+      return pfe::fail(PFE_EBOUNDS,
+                       "filtered vectors grew beyond the filter's bound on [-1, 1]: the "
+                       "spectrum exceeds [lam_lb, lam_ub]");
+    if (info != 0) {
+      if (shifted_done || !(dmax > 0) || !std::isfinite(dmax))
+        return pfe::fail(PFE_EBREAKDOWN, "CholQR breakdown (Gram matrix not positive definite)");
+      const double u = std::ldexp(1.0, -53);
+      const double shift = 11.0 * ((double)n * q + (double)q * (q + 1)) * u * (dmax * q);
+      PFE_HIP(pfe::chol_inv_f64(q, sm.G, shift, sm.Rinv, sm.info, nullptr, h->stream));
+      PFE_HIP(hipMemcpyAsync(&info, sm.info, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+      PFE_TRY(sync(h));
+      if (info != 0)
+        return pfe::fail(PFE_EBREAKDOWN, "shifted CholQR breakdown");
+      shifted_done = true;
+      passes += 1;
+    }
+    PFE_HIP(pfe::gemm_tall_f64(n, q, q, X, ld, sm.Rinv, X, ld, h->stream));
+  }
+  return pfe::ok();
+}
+
+// Rayleigh-Ritz on H: W = H X, S = X^T W, S = Q Theta Q^T, X <- X Q, W <- W Q,
+// residuals ||W_j - theta_j X_j|| / lam_ub.  Theta and residuals to host.
+Err rayleigh_ritz(pfe_handle h, const Small& sm, double* X, double* W, int64_t n, int q,
+                  int64_t ld, std::vector<double>& theta, std::vector<double>& res,
+                  double* t_rr, double* t_res) {
+  const pfe::Bsr A = h->bsr();
+  {
+    Timer tm(h, t_rr);
+    PFE_HIP(pfe::cheb_step_f64(A, h->H.as<double>(), X, nullptr, W, nullptr, q, ld, 1.0, 0.0,
+                               0.0, 0.0, 0.0, 0.0, h->stream));
+    PFE_HIP(pfe::gram_f64(n, q, q, X, ld, W, ld, sm.S, h->wsRed.p, h->stream));
+    PFE_HIP(pfe::sym_eig_f64(q, sm.S, sm.theta, sm.Q, sm.jw, sm.info, h->stream));
+    PFE_HIP(pfe::gemm_tall_f64(n, q, q, X, ld, sm.Q, X, ld, h->stream));
+    PFE_HIP(pfe::gemm_tall_f64(n, q, q, W, ld, sm.Q, W, ld, h->stream));
+  }
+  {
+    Timer tm(h, t_res);
+    PFE_HIP(pfe::resid_norms_f64(n, q, W, X, ld, sm.theta, 1.0 / h->lam_ub, sm.res, h->wsRed.p,
+                                 h->stream));
+    theta.resize(q);
+    res.resize(q);
+    int info = 0;
+    PFE_HIP(hipMemcpyAsync(theta.data(), sm.theta, q * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+    PFE_HIP(hipMemcpyAsync(res.data(), sm.res, q * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+    PFE_HIP(hipMemcpyAsync(&info, sm.info, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    PFE_TRY(sync(h));
+    if (info < 0) return pfe::fail(PFE_EHIP, "Jacobi eigensolver did not converge");
+  }
+  return pfe::ok();
+}
+
+double coef_abs_sum(const std::vector<double>& c) {
+  double s = 0;
+  for (double v : c) s += std::fabs(v);
+  return s;
+}
+
+}  // namespace
+
+// =================================================================== C-ABI
+extern "C" {
+
+const char* pfe_version(void) { return "pfeig 0.1 (gfx950)"; }
+
+pfe_status pfe_create(int device, void* hip_stream, pfe_handle* out) {
+  if (!out) return PFE_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PFE_EHIP;
+  pfe_ctx* h = new pfe_ctx();
+  h->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete h;
+    return PFE_EHIP;
+  }
+  if (hip_stream) {
+    h->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete h;
+      return PFE_EHIP;
+    }
+    h->own_stream = true;
+  }
+  if (hipEventCreate(&h->ev[0]) != hipSuccess || hipEventCreate(&h->ev[1]) != hipSuccess) {
+    delete h;
+    return PFE_EHIP;
+  }
+  if (h->flags.ensure(256) != hipSuccess) {
+    delete h;
+    return PFE_ENOMEM;
+  }
+  *out = h;
+  return PFE_OK;
+}
+
+void pfe_destroy(pfe_handle h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+const char* pfe_last_error(pfe_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+int64_t pfe_device_bytes(pfe_handle h) {
+  if (!h) return 0;
+  const DevBuf* bufs[] = {&h->row_ptr, &h->col_idx, &h->H,    &h->transpose, &h->masses,
+                          &h->H32,     &h->flags,   &h->wsA,  &h->wsB,       &h->wsC,
+                          &h->wsD,     &h->wsSmall, &h->wsRed, &h->wsOut,    &h->wsCk};
+  int64_t s = 0;
+  for (auto* b : bufs) s += (int64_t)b->bytes;
+  return s;
+}
+
+void pfe_solve_opts_default(pfe_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->r = std::pow(0.1, 0.25);
+  o->smoothing = PFE_SMOOTH_NONE;
+  o->tol = 1e-10;
+  o->max_iter = 100;
+  o->precision = PFE_FP64;
+  o->seed = 11;
+}
+
+// ----------------------------------------------------------- set_hessian
+static Err set_hessian_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const int64_t* row_ptr,
+                            const int32_t* col_idx, const double* blocks, const double* masses,
+                            uint32_t flags) {
+  PFE_TRY(select_device(h));
+  if (n_atoms <= 0 || nnzb < n_atoms || !row_ptr || !col_idx || !blocks)
+    return pfe::fail(PFE_EINVAL, "need n_atoms > 0, nnzb >= n_atoms and non-null arrays");
+  if (n_atoms > (int64_t)INT32_MAX / 3 || nnzb >= (int64_t)INT32_MAX)
+    return pfe::fail(PFE_EINVAL, "sizes exceed the 32-bit index range of the kernels");
+  const bool weight = !(flags & PFE_BLOCKS_ARE_H);
+  if (weight && !masses) return pfe::fail(PFE_EINVAL, "masses are required unless PFE_BLOCKS_ARE_H");
+  const bool dev = (flags & PFE_DEVICE_PTRS) != 0;
+  // row pointers checked on the host
+  std::vector<int64_t> rp(n_atoms + 1);
+  if (dev) {
+    PFE_HIP(hipMemcpy(rp.data(), row_ptr, rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(rp.data(), row_ptr, rp.size() * sizeof(int64_t));
+  }
+  if (rp[0] != 0 || rp[n_atoms] != nnzb)
+    return pfe::fail(PFE_EINVAL, "row_ptr must start at 0 and end at nnzb");
+  for (int64_t i = 0; i < n_atoms; ++i)
+    if (rp[i + 1] <= rp[i]) return pfe::fail(PFE_EINVAL, "every block row needs >= 1 block (the diagonal)");
+  h->has_h = h->has_masses = h->has_bounds = false;
+  h->h32_c = h->h32_e = NAN;
+  h->H32.release();
+  h->n_atoms = n_atoms;
+  h->nnzb = nnzb;
+  PFE_HIP(h->row_ptr.ensure((n_atoms + 1) * sizeof(int64_t)));
+  PFE_HIP(h->col_idx.ensure((nnzb + pfe::kBsrPad) * sizeof(int32_t)));
+  PFE_HIP(h->H.ensure((size_t)(nnzb + pfe::kBsrPad) * 9 * sizeof(double)));
+  PFE_HIP(h->transpose.ensure(nnzb * sizeof(int32_t)));
+  PFE_HIP(hipMemsetAsync(h->col_idx.p, 0, (nnzb + pfe::kBsrPad) * sizeof(int32_t), h->stream));
+  PFE_HIP(pfe::zero_f64(h->H.as<double>(), (nnzb + pfe::kBsrPad) * 9, h->stream));
+  PFE_HIP(hipMemcpyAsync(h->row_ptr.p, rp.data(), rp.size() * sizeof(int64_t),
+                         hipMemcpyHostToDevice, h->stream));
+  PFE_TRY(upload(h, h->col_idx.as<int32_t>(), col_idx, nnzb, dev));
+  PFE_TRY(upload(h, h->H.as<double>(), blocks, nnzb * 9, dev));
+  int* eflag = h->flags.as<int>();
+  PFE_HIP(hipMemsetAsync(eflag, 0, sizeof(int), h->stream));
+  const pfe::Bsr A = h->bsr();
+  PFE_HIP(pfe::validate_bsr(A, h->H.as<double>(), h->transpose.as<int32_t>(), eflag, h->stream));
+  if (masses) {
+    PFE_HIP(h->masses.ensure(n_atoms * sizeof(double)));
+    PFE_TRY(upload(h, h->masses.as<double>(), masses, n_atoms, dev));
+    PFE_HIP(pfe::validate_masses(n_atoms, h->masses.as<double>(), eflag, h->stream));
+  }
+  int ef = 0;
+  PFE_HIP(hipMemcpyAsync(&ef, eflag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  PFE_TRY(sync(h));
+  if (ef & 1) return pfe::fail(PFE_EINVAL, "column indices out of range, unsorted, or diagonal block missing");
+  if (ef & 2) return pfe::fail(PFE_EINVAL, "non-finite block value");
+  if (ef & 16) return pfe::fail(PFE_EINVAL, "masses must be finite and > 0");
+  if (ef & 4) return pfe::fail(PFE_ENOTSYM, "a block has no transpose partner");
+  if (ef & 8) return pfe::fail(PFE_ENOTSYM, "a block differs from its partner's transpose");
+  if (weight) {
+    PFE_HIP(pfe::mass_weight(A, h->H.as<double>(), h->masses.as<double>(), h->H.as<double>(),
+                             h->stream));
+  }
+  PFE_TRY(sync(h));
+  h->has_h = true;
+  h->has_masses = masses != nullptr;
+  return pfe::ok();
+}
+
+pfe_status pfe_set_hessian(pfe_handle h, int64_t n_atoms, int64_t nnzb, const int64_t* row_ptr,
+                           const int32_t* col_idx, const double* blocks, const double* masses,
+                           uint32_t flags) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, set_hessian_impl(h, n_atoms, nnzb, row_ptr, col_idx, blocks, masses, flags));
+}
+
+// ----------------------------------------------------------------- bounds
+static Err bounds_impl(pfe_handle h, int m, const double* v0, uint64_t seed, uint32_t flags,
+                       double* lam_lb, double* lam_ub, double* theta_max) {
+  PFE_TRY(select_device(h));
+  if (!h->has_h) return pfe::fail(PFE_ESTATE, "no Hessian set");
+  const int64_t n = h->n();
+  if (m < 2 || m > 512 || m > n) return pfe::fail(PFE_EINVAL, "steps must be in [2, min(512, n)]");
+  const bool dev = (flags & PFE_DEVICE_PTRS) != 0;
+  PFE_HIP(h->wsA.ensure((size_t)(m + 2) * n * sizeof(double)));
+  double* V = h->wsA.as<double>();
+  double* w = V + (int64_t)(m + 1) * n;
+  PFE_HIP(h->wsSmall.ensure((size_t)(4 * m + 8 + 3 * m * m) * sizeof(double) + 64));
+  double* alpha = h->wsSmall.as<double>();
+  double* beta = alpha + m;
+  double* hv = beta + m;
+  double* nrm = hv + m + 4;
+  double* Tm = nrm + 4;
+  double* evals = Tm + (int64_t)m * m;
+  double* Qm = evals + m;
+  PFE_HIP(h->wsRed.ensure(std::max(pfe::multidot_work_bytes(n, m + 1), pfe::colnorm_work_bytes(n, 1)) +
+                          pfe::jacobi_work_bytes(m) + 64));
+  double* red = h->wsRed.as<double>();
+  double* jw = red + std::max(pfe::multidot_work_bytes(n, m + 1), pfe::colnorm_work_bytes(n, 1)) / sizeof(double);
+  int* info = h->flags.as<int>() + 4;
+  if (v0) {
+    PFE_TRY(upload(h, V, v0, n, dev));
+  } else {
+    PFE_HIP(pfe::gaussian_fill_f64(n, 1, V, 1, seed, h->stream));
+  }
+  const pfe::Bsr A = h->bsr();
+  const double* Hv = h->H.as<double>();
+  PFE_HIP(pfe::col_norms_f64(n, 1, V, 1, nrm, red, h->stream));
+  PFE_HIP(pfe::scale_by_inv_f64(n, V, nrm, V, h->stream));
+  for (int j = 0; j < m; ++j) {
+    double* vj = V + (int64_t)j * n;
+    PFE_HIP(pfe::spmv_f64(A, Hv, vj, w, h->stream));
+    PFE_HIP(pfe::multi_dot_f64(n, 1, vj, w, alpha + j, red, h->stream));
+    PFE_HIP(pfe::multi_axpy_f64(n, 1, vj, alpha + j, w, h->stream));
+    if (j > 0) PFE_HIP(pfe::multi_axpy_f64(n, 1, vj - n, beta + j - 1, w, h->stream));
+    for (int pass = 0; pass < 2; ++pass) {
+      PFE_HIP(pfe::multi_dot_f64(n, j + 1, V, w, hv, red, h->stream));
+      PFE_HIP(pfe::multi_axpy_f64(n, j + 1, V, hv, w, h->stream));
+    }
+    PFE_HIP(pfe::col_norms_f64(n, 1, w, 1, beta + j, red, h->stream));
+    PFE_HIP(pfe::scale_by_inv_f64(n, w, beta + j, vj + n, h->stream));
+  }
+  std::vector<double> ha(m), hb(m);
+  PFE_HIP(hipMemcpyAsync(ha.data(), alpha, m * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  PFE_HIP(hipMemcpyAsync(hb.data(), beta, m * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  PFE_TRY(sync(h));
+  // an invariant subspace ends the recurrence early
+  int mm = m;
+  for (int j = 0; j < m; ++j)
+    if (!(hb[j] > 1e-300) || !std::isfinite(hb[j])) {
+      mm = j + 1;
+      break;
+    }
+  for (int j = 0; j < mm; ++j)
+    if (!std::isfinite(ha[j])) return pfe::fail(PFE_EINVAL, "Lanczos produced non-finite values");
+  std::vector<double> Th((size_t)mm * mm, 0.0);
+  for (int j = 0; j < mm; ++j) {
+    Th[(size_t)j * mm + j] = ha[j];
+    if (j + 1 < mm) Th[(size_t)j * mm + j + 1] = Th[(size_t)(j + 1) * mm + j] = hb[j];
+  }
+  PFE_HIP(hipMemcpyAsync(Tm, Th.data(), Th.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  PFE_HIP(pfe::sym_eig_f64(mm, Tm, evals, Qm, jw, info, h->stream));
+  std::vector<double> ev(mm), Qh((size_t)mm * mm);
+  PFE_HIP(hipMemcpyAsync(ev.data(), evals, mm * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  PFE_HIP(hipMemcpyAsync(Qh.data(), Qm, Qh.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  PFE_TRY(sync(h));
+  const double th = ev[mm - 1];
+  const double s_last = Qh[(size_t)(mm - 1) * mm + (mm - 1)];
+  const double bm = (mm == m) ? hb[m - 1] : 0.0;
+  const double ub = th + std::fabs(bm * s_last);
+  h->lam_lb = 0.0;
+  h->lam_ub = ub;
+  h->has_bounds = true;
+  if (lam_lb) *lam_lb = 0.0;
+  if (lam_ub) *lam_ub = ub;
+  if (theta_max) *theta_max = th;
+  return pfe::ok();
+}
+
+pfe_status pfe_estimate_bounds(pfe_handle h, int32_t steps, const double* v0, uint64_t seed,
+                               uint32_t flags, double* lam_lb, double* lam_ub, double* theta_max) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, bounds_impl(h, steps, v0, seed, flags, lam_lb, lam_ub, theta_max));
+}
+
+pfe_status pfe_set_bounds(pfe_handle h, double lam_lb, double lam_ub) {
+  if (!h) return PFE_EINVAL;
+  if (!(lam_ub > lam_lb) || !std::isfinite(lam_lb) || !std::isfinite(lam_ub))
+    return finish(h, pfe::fail(PFE_EINVAL, "need finite lam_lb < lam_ub"));
+  h->lam_lb = lam_lb;
+  h->lam_ub = lam_ub;
+  h->has_bounds = true;
+  return finish(h, pfe::ok());
+}
+
+// ---------------------------------------------------------------- design
+pfe_status pfe_design_filter(double lam_lo, double lam_hi, double lam_lb, double lam_ub,
+                             const pfe_filter_opts* opts, double* coef_out, int32_t coef_cap,
+                             pfe_filter* out) {
+  if (!opts || !out) return PFE_EINVAL;
+  pfe::FilterDesign f;
+  Err e = pfe::design_filter(lam_lo, lam_hi, lam_lb, lam_ub, opts->degree, opts->eps, opts->r,
+                             opts->smoothing, &f);
+  if (e) return e.st;
+  out->degree = f.degree;
+  out->smoothing = f.smoothing;
+  out->c = f.c;
+  out->e = f.e;
+  out->xi = f.xi;
+  out->eta = f.eta;
+  out->eps = f.eps;
+  out->coef = nullptr;
+  if (!coef_out || coef_cap < f.degree + 1) return PFE_ECAPACITY;
+  std::memcpy(coef_out, f.coef.data(), (f.degree + 1) * sizeof(double));
+  out->coef = coef_out;
+  return PFE_OK;
+}
+
+// ----------------------------------------------------------- apply_filter
+static Err apply_impl(pfe_handle h, const pfe_filter* f, int nvec, const void* X, void* Y,
+                      int64_t ld, int precision, uint32_t flags) {
+  PFE_TRY(select_device(h));
+  PFE_TRY(check_filter(h, f));
+  if (nvec < 1 || ld < nvec || !X || !Y) return pfe::fail(PFE_EINVAL, "need 1 <= nvec <= ld and arrays");
+  if (precision != PFE_FP64 && precision != PFE_FP32) return pfe::fail(PFE_EINVAL, "precision");
+  const bool dev = (flags & PFE_DEVICE_PTRS) != 0;
+  const int64_t n = h->n();
+  const size_t elem = precision == PFE_FP64 ? 8 : 4;
+  const size_t mv = (size_t)n * ld * elem;
+  std::vector<double> coef(f->coef, f->coef + f->degree + 1);
+  PFE_HIP(h->wsA.ensure(mv));
+  PFE_HIP(h->wsB.ensure(mv));
+  if (!dev) {
+    PFE_HIP(h->wsC.ensure(mv));
+    PFE_HIP(h->wsD.ensure(mv));
+  }
+  const void* Xd = X;
+  void* Yd = Y;
+  if (!dev) {
+    PFE_HIP(hipMemcpyAsync(h->wsC.p, X, mv, hipMemcpyHostToDevice, h->stream));
+    Xd = h->wsC.p;
+    Yd = h->wsD.p;
+  }
+  if (precision == PFE_FP64) {
+    PFE_TRY(run_filter<double>(h, h->H.as<double>(), coef, 1.0 / f->e, -f->c / f->e, 2.0 / f->e,
+                               -2.0 * f->c / f->e, (double*)Xd, false, (double*)Yd,
+                               h->wsA.as<double>(), h->wsB.as<double>(), nvec, ld, nullptr));
+  } else {
+    PFE_TRY(ensure_h32(h, f->c, f->e));
+    PFE_TRY(run_filter<float>(h, h->H32.as<float>(), coef, 1.0, 0.0, 2.0, 0.0, (float*)Xd, false,
+                              (float*)Yd, h->wsA.as<float>(), h->wsB.as<float>(), nvec, ld,
+                              nullptr));
+  }
+  if (!dev) PFE_HIP(hipMemcpyAsync(Y, Yd, mv, hipMemcpyDeviceToHost, h->stream));
+  PFE_TRY(sync(h));
+  return pfe::ok();
+}
+
+pfe_status pfe_apply_filter(pfe_handle h, const pfe_filter* f, int32_t nvec, const void* X,
+                            void* Y, int64_t ld, int32_t precision, uint32_t flags) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, apply_impl(h, f, nvec, X, Y, ld, precision, flags));
+}
+
+// ------------------------------------------------------------------ solve
+static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
+                      const pfe_solve_opts* o_in, int* n_found, double* evals, double* evecs,
+                      double* resid, pfe_solve_stats* st_out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  PFE_TRY(select_device(h));
+  if (!h->has_h) return pfe::fail(PFE_ESTATE, "no Hessian set");
+  if (!h->has_bounds) return pfe::fail(PFE_ESTATE, "no spectral bounds (estimate_bounds or set_bounds)");
+  pfe_solve_opts o;
+  pfe_solve_opts_default(&o);
+  if (o_in) o = *o_in;
+  if (o.tol <= 0) o.tol = 1e-10;
+  if (o.max_iter <= 0) o.max_iter = 100;
+  if (o.r == 0) o.r = std::pow(0.1, 0.25);
+  const int q = o.block;
+  const int64_t n = h->n();
+  if (q < 1 || q > 256 || q > n) return pfe::fail(PFE_EINVAL, "block must be in [1, min(256, n)]");
+  if (nev < 0 || !n_found) return pfe::fail(PFE_EINVAL, "nev >= 0 and n_found required");
+  if (o.precision != PFE_FP64 && o.precision != PFE_FP32) return pfe::fail(PFE_EINVAL, "precision");
+  if (lam_lo < h->lam_lb || lam_hi > h->lam_ub)
+    return pfe::fail(PFE_EINVAL, "window must lie inside [lam_lb, lam_ub]");
+  pfe::FilterDesign fd;
+  PFE_TRY(pfe::design_filter(lam_lo, lam_hi, h->lam_lb, h->lam_ub, o.degree, o.eps, o.r,
+                             o.smoothing, &fd));
+  pfe_solve_stats st;
+  std::memset(&st, 0, sizeof(st));
+  st.degree = fd.degree;
+  st.eps = fd.eps;
+  st.c = fd.c;
+  st.e = fd.e;
+  st.xi = fd.xi;
+  st.eta = fd.eta;
+
+  const bool mixed = o.precision == PFE_FP32;
+  const char* tr_env = std::getenv("PFEIG_TRACE");
+  const bool trace = tr_env && tr_env[0] && tr_env[0] != '0';
+  const int64_t ld = round_up(q, 8);
+  const size_t mv64 = (size_t)n * ld * sizeof(double);
+  // FP64 form: X, Y, W(T).  Mixed form: X64, W64 and a 12-byte/element
+  // region holding X32, T32, Y32 (or, for the refinement sweep, one FP64 Y).
+  PFE_HIP(h->wsA.ensure(mv64));
+  PFE_HIP(h->wsB.ensure(mv64));
+  PFE_HIP(h->wsC.ensure(mixed ? (size_t)n * ld * 12 : mv64));
+  double* X = h->wsA.as<double>();
+  double* W = h->wsB.as<double>();
+  char* R = h->wsC.as<char>();
+  PFE_HIP(pfe::zero_f64(X, n * ld, h->stream));
+  PFE_HIP(pfe::zero_f64(W, n * ld, h->stream));
+  PFE_HIP(pfe::zero_f64((double*)R, (int64_t)(mixed ? n * ld * 12 : mv64) / 8, h->stream));
+  Small sm;
+  PFE_TRY(alloc_small(h, q, &sm));
+  PFE_TRY(ensure_red(h, n, q));
+  if (o.x0) {
+    if (o.flags & PFE_DEVICE_PTRS) {
+      PFE_HIP(pfe::copy_cols_f64(n, q, o.x0, q, X, ld, h->stream));
+    } else {
+      PFE_HIP(hipMemcpy2DAsync(X, ld * sizeof(double), o.x0, q * sizeof(double), q * sizeof(double),
+                               n, hipMemcpyHostToDevice, h->stream));
+    }
+  } else {
+    PFE_HIP(pfe::gaussian_fill_f64(n, q, X, ld, o.seed, h->stream));
+  }
+  if (mixed) PFE_TRY(ensure_h32(h, fd.c, fd.e));
+  const double bound = 1.05 * coef_abs_sum(fd.coef) + 1e-12;
+  const double sbytes64 = step_bytes(h->n_atoms, h->nnzb, q, 8);
+  const double sbytes32 = step_bytes(h->n_atoms, h->nnzb, q, 4);
+  {
+    Timer tm(h, &st.t_orth);
+    PFE_TRY(cholqr2(h, sm, X, n, q, ld, -1.0));
+  }
+  const double delta = 1e-6 * h->lam_ub;
+  std::vector<double> theta, res;
+  int prev_cnt = -1;
+  bool prev_ok = false;
+  bool converged = false;
+  bool fp64_phase = !mixed;
+  double prev_max = HUGE_VAL;
+  const pfe::Bsr A = h->bsr();
+  for (int it = 1; it <= o.max_iter; ++it) {
+    double* Y;
+    if (fp64_phase) {
+      // Y = p(H_hat) X in FP64; X is consumed (t_2 lands there)
+      Y = mixed ? (double*)R : W;
+      double* T1 = mixed ? W : (double*)R;
+      Timer tm(h, &st.t_filter);
+      PFE_TRY(run_filter<double>(h, h->H.as<double>(), fd.coef, 1.0 / fd.e, -fd.c / fd.e,
+                                 2.0 / fd.e, -2.0 * fd.c / fd.e, X, true, Y, T1, nullptr, q, ld,
+                                 &st.filter_steps));
+      st.filter_bytes += sbytes64 * fd.degree;
+      st.fp64_iterations++;
+    } else {
+      float* X32 = (float*)R;
+      float* T32 = X32 + n * ld;
+      float* Y32 = T32 + n * ld;
+      Timer tm(h, &st.t_filter);
+      PFE_HIP(pfe::cast_f64_to_f32(n, q, X, ld, X32, ld, h->stream));
+      PFE_TRY(run_filter<float>(h, h->H32.as<float>(), fd.coef, 1.0, 0.0, 2.0, 0.0, X32, true,
+                                Y32, T32, nullptr, q, ld, &st.filter_steps));
+      PFE_HIP(pfe::cast_f32_to_f64(n, q, Y32, ld, X, ld, h->stream));
+      st.filter_bytes += sbytes32 * fd.degree;
+      Y = X;
+    }
+    {
+      Timer tm(h, &st.t_orth);
+      PFE_TRY(cholqr2(h, sm, Y, n, q, ld, bound));
+    }
+    if (Y != X) {
+      // make X the orthonormal basis and keep W free for H X
+      if (mixed) {
+        PFE_HIP(pfe::copy_cols_f64(n, q, Y, ld, X, ld, h->stream));
+      } else {
+        std::swap(h->wsA.p, h->wsB.p);
+        std::swap(h->wsA.bytes, h->wsB.bytes);
+        X = h->wsA.as<double>();
+        W = h->wsB.as<double>();
+      }
+    }
+    PFE_TRY(rayleigh_ritz(h, sm, X, W, n, q, ld, theta, res, &st.t_rr, &st.t_resid));
+    st.iterations = it;
+    int cnt = 0;
+    bool ok_all = true;
+    double mx = 0.0;
+    for (int j = 0; j < q; ++j) {
+      if (theta[j] >= lam_lo - delta && theta[j] <= lam_hi + delta) {
+        ok_all = ok_all && res[j] <= o.tol;
+        mx = std::max(mx, res[j]);
+      }
+      if (theta[j] >= lam_lo && theta[j] <= lam_hi) ++cnt;
+    }
+    if (trace)
+      std::fprintf(stderr, "[pfeig] it %d %s in-window %d max-resid(near) %.3e t=%.3fs\n", it,
+                   fp64_phase ? "fp64" : "fp32", cnt, mx,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    if (fp64_phase && st.refined) {
+      converged = ok_all;
+      break;   // the single refinement sweep is over
+    }
+    if (ok_all && prev_ok && cnt == prev_cnt) {
+      converged = true;
+      break;
+    }
+    if (!fp64_phase && it >= 2 && cnt == prev_cnt &&
+        (mx > 0.5 * prev_max || mx <= 30.0 * o.tol)) {
+      // FP32 iterations have stalled (or are within reach of tol): one FP64 sweep
+      fp64_phase = true;
+      st.refined = 1;
+    }
+    prev_ok = ok_all;
+    prev_cnt = cnt;
+    prev_max = mx;
+  }
+  st.gemm_flops = 0;
+  // in-window selection (ascending theta)
+  std::vector<int> sel;
+  for (int j = 0; j < q; ++j)
+    if (theta[j] >= lam_lo && theta[j] <= lam_hi && (converged || res[j] <= o.tol)) sel.push_back(j);
+  int total_in = 0;
+  for (int j = 0; j < q; ++j)
+    if (theta[j] >= lam_lo && theta[j] <= lam_hi) ++total_in;
+  st.n_window = total_in;
+  const auto t1 = std::chrono::steady_clock::now();
+  st.t_total = std::chrono::duration<double>(t1 - t0).count();
+  if (st_out) *st_out = st;
+  if (total_in > nev) {
+    *n_found = total_in;
+    return pfe::fail(PFE_ECAPACITY, "more eigenvalues in the window than nev");
+  }
+  const int ns = (int)sel.size();
+  *n_found = ns;
+  double maxr = 0;
+  for (int s = 0; s < ns; ++s) {
+    if (evals) evals[s] = theta[sel[s]];
+    if (resid) resid[s] = res[sel[s]];
+    maxr = std::max(maxr, res[sel[s]]);
+  }
+  if (evecs && ns > 0) {
+    PFE_HIP(hipMemcpyAsync(sm.sel, sel.data(), ns * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    const bool dev_out = (o.flags & PFE_DEVICE_PTRS) != 0;
+    double* dst = evecs;
+    if (!dev_out) {
+      PFE_HIP(h->wsOut.ensure((size_t)ns * n * sizeof(double)));
+      dst = h->wsOut.as<double>();
+    }
+    PFE_HIP(pfe::gather_transpose_signfix(n, ns, X, ld, sm.sel, dst, h->wsRed.p, h->stream));
+    if (!dev_out)
+      PFE_HIP(hipMemcpyAsync(evecs, dst, (size_t)ns * n * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+    PFE_TRY(sync(h));
+  }
+  st.max_resid = maxr;
+  st.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st_out) *st_out = st;
+  (void)A;
+  if (!converged) return pfe::fail(PFE_ENOCONV, "not converged within max_iter (or after the refinement sweep)");
+  return pfe::ok();
+}
+
+pfe_status pfe_solve_interval(pfe_handle h, double lam_lo, double lam_hi, int32_t nev,
+                              const pfe_solve_opts* opts, int32_t* n_found, double* evals,
+                              double* evecs, double* resid, pfe_solve_stats* stats) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, solve_impl(h, lam_lo, lam_hi, nev, opts, n_found, evals, evecs, resid, stats));
+}
+
+// ------------------------------------------------------------------ count
+static Err count_impl(pfe_handle h, double lam_lo, double lam_hi, int degree, int smoothing,
+                      int M, const double* V, uint64_t seed, uint32_t flags, double* count) {
+  PFE_TRY(select_device(h));
+  if (!h->has_h) return pfe::fail(PFE_ESTATE, "no Hessian set");
+  if (!h->has_bounds) return pfe::fail(PFE_ESTATE, "no spectral bounds");
+  if (degree < 0 || M < 1 || !count || smoothing < 0 || smoothing > 2)
+    return pfe::fail(PFE_EINVAL, "degree >= 0, nsamples >= 1, smoothing, count");
+  const int64_t n = h->n();
+  const double c = 0.5 * (h->lam_ub + h->lam_lb), e = 0.5 * (h->lam_ub - h->lam_lb);
+  std::vector<double> coef = pfe::chi_coefficients((lam_lo - c) / e, (lam_hi - c) / e, degree, smoothing);
+  const int64_t ld = round_up(M, 8);
+  const size_t mv = (size_t)n * ld * sizeof(double);
+  PFE_HIP(h->wsA.ensure(mv));
+  PFE_HIP(h->wsB.ensure(mv));
+  PFE_HIP(h->wsC.ensure(mv));
+  PFE_HIP(h->wsD.ensure(mv));
+  double* Vd = h->wsA.as<double>();
+  PFE_HIP(pfe::zero_f64(Vd, n * ld, h->stream));
+  if (V) {
+    if (flags & PFE_DEVICE_PTRS) {
+      PFE_HIP(pfe::copy_cols_f64(n, M, V, M, Vd, ld, h->stream));
+    } else {
+      PFE_HIP(hipMemcpy2DAsync(Vd, ld * sizeof(double), V, M * sizeof(double), M * sizeof(double),
+                               n, hipMemcpyHostToDevice, h->stream));
+    }
+  } else {
+    PFE_HIP(pfe::gaussian_fill_f64(n, M, Vd, ld, seed, h->stream));
+  }
+  PFE_TRY(ensure_red(h, n, M));
+  PFE_HIP(h->wsSmall.ensure((size_t)2 * M * sizeof(double) + 64));
+  double* nrm = h->wsSmall.as<double>();
+  double* dots = nrm + M;
+  PFE_HIP(pfe::col_norms_f64(n, M, Vd, ld, nrm, h->wsRed.p, h->stream));
+  PFE_HIP(pfe::col_scale_inv_f64(n, M, Vd, ld, nrm, h->stream));
+  // keep the unit samples in wsD; the filter consumes only copies
+  double* Vk = h->wsD.as<double>();
+  PFE_HIP(pfe::copy_cols_f64(n, (int)ld, Vd, ld, Vk, ld, h->stream));
+  double* Y = h->wsB.as<double>();
+  PFE_TRY(run_filter<double>(h, h->H.as<double>(), coef, 1.0 / e, -c / e, 2.0 / e, -2.0 * c / e,
+                             Vd, true, Y, h->wsC.as<double>(), nullptr, M, ld, nullptr));
+  PFE_HIP(pfe::col_dots_f64(n, M, Vk, Y, ld, dots, h->wsRed.p, h->stream));
+  std::vector<double> hd(M);
+  PFE_HIP(hipMemcpyAsync(hd.data(), dots, M * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  PFE_TRY(sync(h));
+  double s = 0;
+  for (double v : hd) s += v;
+  *count = (double)n / M * s;
+  return pfe::ok();
+}
+
+pfe_status pfe_estimate_count(pfe_handle h, double lam_lo, double lam_hi, int32_t degree,
+                              int32_t smoothing, int32_t nsamples, const double* V, uint64_t seed,
+                              uint32_t flags, double* count) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, count_impl(h, lam_lo, lam_hi, degree, smoothing, nsamples, V, seed, flags,
+                              count));
+}
+
+// ---------------------------------------------------------------- adjoint
+static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const double* X,
+                        const double* dY, double* dX, double* dblocks, int64_t ld, int stride,
+                        uint32_t flags) {
+  PFE_TRY(select_device(h));
+  PFE_TRY(check_filter(h, f));
+  if (nvec < 1 || nvec > 256 || ld < nvec || !X || !dY || !dX || !dblocks)
+    return pfe::fail(PFE_EINVAL, "need 1 <= nvec <= 256, nvec <= ld and non-null arrays");
+  const bool dev = (flags & PFE_DEVICE_PTRS) != 0;
+  const int64_t n = h->n();
+  const int d = f->degree;
+  const double c = f->c, e = f->e;
+  const int s = stride > 0 ? stride : std::max(1, (int)std::ceil(std::sqrt((double)std::max(d, 1))));
+  const int nseg = d > 0 ? (d + s - 1) / s : 0;
+  const size_t mv = (size_t)n * ld * sizeof(double);
+  const int64_t nel = n * ld;
+  // device: X, Ybar, a0/a1 pair, segment buffer (s vectors), checkpoints (2 per segment)
+  PFE_HIP(h->wsA.ensure(mv * 2));                 // X, Ybar (device copies when host inputs)
+  PFE_HIP(h->wsB.ensure(mv * 2));                 // a buffers
+  PFE_HIP(h->wsC.ensure(mv * (size_t)std::max(s, 1)));
+  PFE_HIP(h->wsCk.ensure(mv * (size_t)std::max(2 * nseg, 1)));
+  PFE_HIP(h->wsD.ensure((size_t)(h->nnzb + 1) * 9 * sizeof(double)));
+  const double* Xd = X;
+  const double* Yb = dY;
+  if (!dev) {
+    PFE_HIP(hipMemcpyAsync(h->wsA.p, X, mv, hipMemcpyHostToDevice, h->stream));
+    PFE_HIP(hipMemcpyAsync(h->wsA.as<double>() + nel, dY, mv, hipMemcpyHostToDevice, h->stream));
+    Xd = h->wsA.as<double>();
+    Yb = h->wsA.as<double>() + nel;
+  }
+  double* aA = h->wsB.as<double>();
+  double* aB = aA + nel;
+  double* seg = h->wsC.as<double>();
+  double* ck = h->wsCk.as<double>();
+  double* G = h->wsD.as<double>();
+  const pfe::Bsr A = h->bsr();
+  const double* Hv = h->H.as<double>();
+  const int32_t* tr = h->transpose.as<int32_t>();
+  PFE_HIP(pfe::zero_f64(G, h->nnzb * 9, h->stream));
+  const double a1 = 1.0 / e, b1 = -c / e, a2 = 2.0 / e, b2 = -2.0 * c / e;
+  auto fwd = [&](const double* tin, const double* prev, double* out, bool first) -> hipError_t {
+    return pfe::cheb_step_f64(A, Hv, tin, prev, out, nullptr, nvec, ld, first ? a1 : a2,
+                              first ? b1 : b2, first ? 0.0 : -1.0, 0.0, 0.0, 0.0, h->stream);
+  };
+  // forward sweep storing (t_{js}, t_{js+1}) for every segment j
+  if (d >= 1) {
+    double* t_prev = seg;                         // rolling pair in seg[0], seg[1] (s >= 1)
+    double* t_cur = (s >= 2) ? seg + nel : aA;
+    PFE_HIP(pfe::copy_cols_f64(n, (int)ld, Xd, ld, t_prev, ld, h->stream));
+    PFE_HIP(fwd(Xd, nullptr, t_cur, true));       // t_1
+    for (int k = 1; k <= d - 1; ++k) {
+      // invariant: t_prev = t_{k-1}, t_cur = t_k
+      if ((k - 1) % s == 0) {
+        const int j = (k - 1) / s;
+        PFE_HIP(pfe::copy_cols_f64(n, (int)ld, t_prev, ld, ck + (2 * j) * nel, ld, h->stream));
+        PFE_HIP(pfe::copy_cols_f64(n, (int)ld, t_cur, ld, ck + (2 * j + 1) * nel, ld, h->stream));
+      }
+      PFE_HIP(fwd(t_cur, t_prev, t_prev, false));  // t_{k+1} over t_{k-1}
+      std::swap(t_prev, t_cur);
+    }
+    if ((d - 1) % s == 0) {   // last segment starts at d-1 (only t_{d-1} is needed)
+      const int j = (d - 1) / s;
+      PFE_HIP(pfe::copy_cols_f64(n, (int)ld, t_prev, ld, ck + (2 * j) * nel, ld, h->stream));
+      PFE_HIP(pfe::copy_cols_f64(n, (int)ld, t_cur, ld, ck + (2 * j + 1) * nel, ld, h->stream));
+    }
+  }
+  // reverse sweep: a_d = g_d Ybar; a_k = g_k Ybar + 2 A a_{k+1} - a_{k+2};
+  // a_0 = g_0 Ybar + A a_1 - a_2; G += w_k a_{k+1} t_k^T (w_0 = 1, else 2).
+  double* a_hi = aA;   // a_{k+2}
+  double* a_mid = aB;  // a_{k+1}
+  PFE_HIP(pfe::zero_f64(a_hi, nel, h->stream));
+  PFE_HIP(pfe::copy_cols_f64(n, (int)ld, Yb, ld, a_mid, ld, h->stream));
+  PFE_HIP(pfe::scale_f64(nel, f->coef[d], a_mid, h->stream));
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int k0 = j * s;
+    const int k1 = std::min(k0 + s, d);          // segment covers t_k, k0 <= k < k1
+    // regenerate t_{k0} .. t_{k1-1} into seg[0 .. k1-k0-1]
+    PFE_HIP(pfe::copy_cols_f64(n, (int)ld, ck + (2 * j) * nel, ld, seg, ld, h->stream));
+    if (k1 - k0 >= 2)
+      PFE_HIP(pfe::copy_cols_f64(n, (int)ld, ck + (2 * j + 1) * nel, ld, seg + nel, ld, h->stream));
+    for (int k = k0 + 2; k < k1; ++k)
+      PFE_HIP(pfe::cheb_step_f64(A, Hv, seg + (k - 1 - k0) * nel, seg + (k - 2 - k0) * nel,
+                                 seg + (k - k0) * nel, nullptr, nvec, ld, a2, b2, -1.0, 0.0, 0.0,
+                                 0.0, h->stream));
+    for (int k = k1 - 1; k >= k0; --k) {
+      const double* tk = seg + (k - k0) * nel;
+      const bool last = (k == 0);
+      // a_k into a_hi's buffer (in place over a_{k+2})
+      PFE_HIP(pfe::adjoint_step_f64(A, tr, Hv, a_mid, a_hi, Yb, a_hi, tk, G, nvec, ld,
+                                    last ? a1 : a2, last ? b1 : b2, -1.0, f->coef[k],
+                                    last ? 1.0 : 2.0, h->stream));
+      std::swap(a_hi, a_mid);   // now a_mid = a_k, a_hi = a_{k+1}
+    }
+  }
+  // a_mid holds a_0 (or a_d = g_0 Ybar when d == 0)
+  PFE_HIP(pfe::scale_f64(h->nnzb * 9, 1.0 / e, G, h->stream));
+  if (dev) {
+    PFE_HIP(pfe::copy_cols_f64(n, (int)ld, a_mid, ld, dX, ld, h->stream));
+    PFE_HIP(hipMemcpyAsync(dblocks, G, h->nnzb * 9 * sizeof(double), hipMemcpyDeviceToDevice,
+                           h->stream));
+  } else {
+    PFE_HIP(hipMemcpyAsync(dX, a_mid, mv, hipMemcpyDeviceToHost, h->stream));
+    PFE_HIP(hipMemcpyAsync(dblocks, G, h->nnzb * 9 * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+  }
+  PFE_TRY(sync(h));
+  return pfe::ok();
+}
+
+pfe_status pfe_apply_filter_adjoint(pfe_handle h, const pfe_filter* f, int32_t nvec,
+                                    const double* X, const double* dY, double* dX,
+                                    double* dblocks, int64_t ld, int32_t ckpt_stride,
+                                    uint32_t flags) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, adjoint_impl(h, f, nvec, X, dY, dX, dblocks, ld, ckpt_stride, flags));
+}
+
+// ----------------------------------------------------- gradient helpers
+static Err eigvec_grad_impl(pfe_handle h, int nvec, const double* V, const double* w,
+                            double* dblocks, uint32_t flags) {
+  PFE_TRY(select_device(h));
+  if (!h->has_h) return pfe::fail(PFE_ESTATE, "no Hessian set");
+  if (nvec < 1 || nvec > 256 || !V || !dblocks) return pfe::fail(PFE_EINVAL, "1 <= nvec <= 256");
+  const bool dev = (flags & PFE_DEVICE_PTRS) != 0;
+  const int64_t n = h->n();
+  const int64_t ld = round_up(nvec, 8);
+  PFE_HIP(h->wsA.ensure((size_t)n * nvec * sizeof(double)));
+  PFE_HIP(h->wsB.ensure((size_t)n * ld * sizeof(double)));
+  PFE_HIP(h->wsD.ensure((size_t)(h->nnzb + 1) * 9 * sizeof(double)));
+  PFE_HIP(h->wsSmall.ensure((size_t)nvec * sizeof(double) + 64));
+  const double* Vd = V;
+  if (!dev) {
+    PFE_HIP(hipMemcpyAsync(h->wsA.p, V, (size_t)n * nvec * sizeof(double), hipMemcpyHostToDevice,
+                           h->stream));
+    Vd = h->wsA.as<double>();
+  }
+  double* Vr = h->wsB.as<double>();
+  PFE_HIP(pfe::zero_f64(Vr, n * ld, h->stream));
+  PFE_HIP(pfe::transpose_to_rows(nvec, n, Vd, Vr, ld, h->stream));
+  const double* wd = nullptr;
+  if (w) {
+    PFE_TRY(upload(h, h->wsSmall.as<double>(), w, nvec, dev));
+    wd = h->wsSmall.as<double>();
+  }
+  double* G = dev ? dblocks : h->wsD.as<double>();
+  PFE_HIP(pfe::sddmm_f64(h->bsr(), nvec, Vr, Vr, ld, wd, G, false, h->stream));
+  if (!dev)
+    PFE_HIP(hipMemcpyAsync(dblocks, G, h->nnzb * 9 * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+  PFE_TRY(sync(h));
+  return pfe::ok();
+}
+
+pfe_status pfe_eigvec_block_gradient(pfe_handle h, int32_t nvec, const double* V, const double* w,
+                                     double* dblocks, uint32_t flags) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, eigvec_grad_impl(h, nvec, V, w, dblocks, flags));
+}
+
+static Err spring_grad_impl(pfe_handle h, int64_t P, const int64_t* pairs, const double* unit,
+                            const double* dblocks, double* dk, double* dm, uint32_t flags) {
+  PFE_TRY(select_device(h));
+  if (!h->has_h) return pfe::fail(PFE_ESTATE, "no Hessian set");
+  if (!h->has_masses) return pfe::fail(PFE_ESTATE, "masses were not given to set_hessian");
+  if (P < 0 || (P > 0 && (!pairs || !unit || !dk)) || !dblocks || !dm)
+    return pfe::fail(PFE_EINVAL, "arrays");
+  const bool dev = (flags & PFE_DEVICE_PTRS) != 0;
+  const int64_t N = h->n_atoms;
+  // host pairs are checked here; device pairs by the kernel's block lookup
+  if (!dev)
+    for (int64_t p = 0; p < P; ++p)
+      if (pairs[2 * p] < 0 || pairs[2 * p] >= N || pairs[2 * p + 1] < 0 || pairs[2 * p + 1] >= N ||
+          pairs[2 * p] == pairs[2 * p + 1])
+        return pfe::fail(PFE_EINVAL, "spring pair out of range");
+  const size_t bG = (size_t)h->nnzb * 9 * sizeof(double);
+  const size_t need = bG + (size_t)P * (16 + 24 + 8) + (size_t)N * 8 + 256;
+  PFE_HIP(h->wsA.ensure(need));
+  char* base = h->wsA.as<char>();
+  double* G = (double*)base;
+  int64_t* pr = (int64_t*)(base + bG);
+  double* un = (double*)(pr + 2 * P);
+  double* dkd = un + 3 * P;
+  double* dmd = dkd + P;
+  const int64_t* prs = pairs;
+  const double* uns = unit;
+  const double* Gs = dblocks;
+  if (!dev) {
+    PFE_TRY(upload(h, pr, pairs, 2 * P, false));
+    PFE_TRY(upload(h, un, unit, 3 * P, false));
+    PFE_TRY(upload(h, G, dblocks, h->nnzb * 9, false));
+    prs = pr;
+    uns = un;
+    Gs = G;
+  }
+  int* eflag = h->flags.as<int>();
+  PFE_HIP(hipMemsetAsync(eflag, 0, sizeof(int), h->stream));
+  PFE_HIP(pfe::spring_chain(h->bsr(), h->transpose.as<int32_t>(), h->H.as<double>(),
+                            h->masses.as<double>(), Gs, P, prs, uns, dev ? dk : dkd,
+                            dev ? dm : dmd, eflag, h->stream));
+  int ef = 0;
+  PFE_HIP(hipMemcpyAsync(&ef, eflag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  if (!dev) {
+    PFE_TRY(download(h, dk, dkd, P, false));
+    PFE_TRY(download(h, dm, dmd, N, false));
+  }
+  PFE_TRY(sync(h));
+  if (ef & 2) return pfe::fail(PFE_EINVAL, "spring pair out of range");
+  if (ef) return pfe::fail(PFE_EINVAL, "a spring's blocks are not stored in the Hessian");
+  return pfe::ok();
+}
+
+pfe_status pfe_spring_gradient(pfe_handle h, int64_t n_springs, const int64_t* pairs,
+                               const double* unit, const double* dblocks, double* dk, double* dm,
+                               uint32_t flags) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, spring_grad_impl(h, n_springs, pairs, unit, dblocks, dk, dm, flags));
+}
+
+}  // extern "C"

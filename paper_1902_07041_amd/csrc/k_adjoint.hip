@@ -1,0 +1,276 @@
+// Reverse mode of the Chebyshev filter (no counterpart in the paper; it is
+// the chain rule applied to Algorithm 2) and the gradient kernels.
+//
+// Reverse step, one wavefront per atom row i (the forward step's mapping):
+//   out_i = alpha (H a)_i + beta a_i + delta prev_i + zeta ybar_i
+// and, when t != nullptr, the block-gradient contribution
+//   G[(j, i)] += gw * a_j t_i^T      for every stored block (i, j),
+// a 3x3 matrix of dot products over the q columns, reduced across the wave.
+// Block (j, i) is found through the transpose map and is written only by the
+// wave of row i, so the accumulation needs no atomics and is deterministic.
+#include "internal.h"
+
+namespace pfe {
+namespace {
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Columns per lane: NP passes of one double (chunk = lane + 64 p).
+template <int NP>
+__global__ __launch_bounds__(256) void k_adj_step(
+    int n_atoms, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+    const int32_t* __restrict__ transpose, const double* __restrict__ vals,
+    const double* __restrict__ a_in, const double* prev, const double* __restrict__ ybar,
+    double* out, const double* __restrict__ t, double* G, int q, int64_t ld, double alpha,
+    double beta, double delta, double zeta, double gw) {
+  const int wave = uniform(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int row = uniform(blockIdx.x * 4 + wave);
+  if (row >= n_atoms) return;
+  double acc[3][NP], tr[3][NP];
+  bool act[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    act[p] = lane + 64 * p < q;
+    for (int a = 0; a < 3; ++a) {
+      acc[a][p] = 0.0;
+      tr[a][p] = 0.0;
+    }
+  }
+  const bool grad = (t != nullptr);
+  if (grad) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+      if (act[p])
+        for (int a = 0; a < 3; ++a) tr[a][p] = t[(int64_t)(3 * row + a) * ld + lane + 64 * p];
+  }
+  const int64_t b0 = row_ptr[row], b1 = row_ptr[row + 1];
+  for (int64_t k = b0; k < b1; ++k) {
+    const int j = col_idx[k];
+    const double* hv = vals + k * 9;
+    double h[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) h[s] = hv[s];
+    double x[3][NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      for (int a = 0; a < 3; ++a)
+        x[a][p] = act[p] ? a_in[(int64_t)(3 * j + a) * ld + lane + 64 * p] : 0.0;
+      acc[0][p] += h[0] * x[0][p] + h[1] * x[1][p] + h[2] * x[2][p];
+      acc[1][p] += h[3] * x[0][p] + h[4] * x[1][p] + h[5] * x[2][p];
+      acc[2][p] += h[6] * x[0][p] + h[7] * x[1][p] + h[8] * x[2][p];
+    }
+    if (grad) {
+      const int tb = transpose[k];
+      double g[9];
+#pragma unroll
+      for (int pa = 0; pa < 3; ++pa)
+#pragma unroll
+        for (int qb = 0; qb < 3; ++qb) {
+          double s = 0.0;
+#pragma unroll
+          for (int p = 0; p < NP; ++p) s += x[pa][p] * tr[qb][p];
+          g[pa * 3 + qb] = wave_sum(s);
+        }
+      if (lane < 9) {
+        double v = 0.0;
+#pragma unroll
+        for (int s = 0; s < 9; ++s)
+          if (lane == s) v = g[s];
+        G[(int64_t)tb * 9 + lane] += gw * v;
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    if (!act[p]) continue;
+    for (int a = 0; a < 3; ++a) {
+      const int64_t off = (int64_t)(3 * row + a) * ld + lane + 64 * p;
+      double o = alpha * acc[a][p];
+      if (beta != 0.0) o += beta * a_in[off];
+      if (delta != 0.0) o += delta * prev[off];
+      if (zeta != 0.0) o += zeta * ybar[off];
+      out[off] = o;
+    }
+  }
+}
+
+// G[b] (+)= sum_c w_c a[3i+p][c] t[3j+q][c] for stored b = (i, j): rows of a
+// are the wave's own, rows of t are gathered.
+template <int NP>
+__global__ __launch_bounds__(256) void k_sddmm(int n_atoms, const int64_t* __restrict__ row_ptr,
+                                               const int32_t* __restrict__ col_idx, int q,
+                                               const double* __restrict__ a,
+                                               const double* __restrict__ t, int64_t ld,
+                                               const double* __restrict__ colw, double* G,
+                                               int accumulate) {
+  const int wave = uniform(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int row = uniform(blockIdx.x * 4 + wave);
+  if (row >= n_atoms) return;
+  double ar[3][NP];
+  bool act[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int c = lane + 64 * p;
+    act[p] = c < q;
+    const double w = (act[p] && colw) ? colw[c] : 1.0;
+    for (int r = 0; r < 3; ++r) ar[r][p] = act[p] ? w * a[(int64_t)(3 * row + r) * ld + c] : 0.0;
+  }
+  for (int64_t k = row_ptr[row]; k < row_ptr[row + 1]; ++k) {
+    const int j = col_idx[k];
+    double x[3][NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+      for (int r = 0; r < 3; ++r)
+        x[r][p] = act[p] ? t[(int64_t)(3 * j + r) * ld + lane + 64 * p] : 0.0;
+    double g[9];
+#pragma unroll
+    for (int pa = 0; pa < 3; ++pa)
+#pragma unroll
+      for (int qb = 0; qb < 3; ++qb) {
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) s += ar[pa][p] * x[qb][p];
+        g[pa * 3 + qb] = wave_sum(s);
+      }
+    if (lane < 9) {
+      double v = 0.0;
+#pragma unroll
+      for (int s = 0; s < 9; ++s)
+        if (lane == s) v = g[s];
+      if (accumulate)
+        G[k * 9 + lane] += v;
+      else
+        G[k * 9 + lane] = v;
+    }
+  }
+}
+
+__device__ int64_t find_block(const int64_t* row_ptr, const int32_t* col_idx, int i, int j) {
+  int64_t lo = row_ptr[i], hi = row_ptr[i + 1] - 1;
+  while (lo <= hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int c = col_idx[mid];
+    if (c == j) return mid;
+    if (c < j)
+      lo = mid + 1;
+    else
+      hi = mid - 1;
+  }
+  return -1;
+}
+
+__global__ void k_spring_dk(int64_t P, int n_atoms, const int64_t* __restrict__ row_ptr,
+                            const int32_t* __restrict__ col_idx, const double* __restrict__ m,
+                            const double* __restrict__ G, const int64_t* __restrict__ pairs,
+                            const double* __restrict__ unit, double* __restrict__ dk, int* err) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int64_t pi = pairs[2 * p], pj = pairs[2 * p + 1];
+  if (pi < 0 || pi >= n_atoms || pj < 0 || pj >= n_atoms || pi == pj) {
+    atomicOr(err, 2);
+    dk[p] = 0.0;
+    return;
+  }
+  const int i = (int)pi, j = (int)pj;
+  const int64_t bii = find_block(row_ptr, col_idx, i, i);
+  const int64_t bjj = find_block(row_ptr, col_idx, j, j);
+  const int64_t bij = find_block(row_ptr, col_idx, i, j);
+  const int64_t bji = find_block(row_ptr, col_idx, j, i);
+  if (bii < 0 || bjj < 0 || bij < 0 || bji < 0) {
+    atomicOr(err, 1);
+    dk[p] = 0.0;
+    return;
+  }
+  const double u[3] = {unit[3 * p], unit[3 * p + 1], unit[3 * p + 2]};
+  const double wi = 1.0 / m[i], wj = 1.0 / m[j], wij = 1.0 / sqrt(m[i] * m[j]);
+  double s = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const int e = a * 3 + b;
+      s += u[a] * u[b] *
+           (G[bii * 9 + e] * wi + G[bjj * 9 + e] * wj - (G[bij * 9 + e] + G[bji * 9 + e]) * wij);
+    }
+  dk[p] = s;
+}
+
+__global__ void k_spring_dm(int n_atoms, const int64_t* __restrict__ row_ptr,
+                            const int32_t* __restrict__ transpose, const double* __restrict__ H,
+                            const double* __restrict__ m, const double* __restrict__ G,
+                            double* __restrict__ dm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_atoms) return;
+  double s = 0.0;
+  for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+    const int64_t t = transpose[k];
+    for (int e = 0; e < 9; ++e) s += G[k * 9 + e] * H[k * 9 + e] + G[t * 9 + e] * H[t * 9 + e];
+  }
+  dm[i] = -0.5 * s / m[i];
+}
+
+inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t adjoint_step_f64(const Bsr& A, const int32_t* transpose, const double* vals,
+                            const double* a_in, const double* prev, const double* ybar,
+                            double* out, const double* t, double* G, int q, int64_t ld,
+                            double alpha, double beta, double delta, double zeta, double gw,
+                            hipStream_t s) {
+  if (A.n_atoms == 0 || q == 0) return hipSuccess;
+  const unsigned grid = nb(A.n_atoms, 4);
+  if (q <= 64)
+    hipLaunchKernelGGL(k_adj_step<1>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
+                       A.col_idx, transpose, vals, a_in, prev, ybar, out, t, G, q, ld, alpha,
+                       beta, delta, zeta, gw);
+  else if (q <= 128)
+    hipLaunchKernelGGL(k_adj_step<2>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
+                       A.col_idx, transpose, vals, a_in, prev, ybar, out, t, G, q, ld, alpha,
+                       beta, delta, zeta, gw);
+  else if (q <= 256)
+    hipLaunchKernelGGL(k_adj_step<4>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
+                       A.col_idx, transpose, vals, a_in, prev, ybar, out, t, G, q, ld, alpha,
+                       beta, delta, zeta, gw);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t sddmm_f64(const Bsr& A, int q, const double* a, const double* t, int64_t ld,
+                     const double* colw, double* G, bool accumulate, hipStream_t s) {
+  if (A.n_atoms == 0) return hipSuccess;
+  const unsigned grid = nb(A.n_atoms, 4);
+  if (q <= 64)
+    hipLaunchKernelGGL(k_sddmm<1>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
+                       A.col_idx, q, a, t, ld, colw, G, accumulate ? 1 : 0);
+  else if (q <= 128)
+    hipLaunchKernelGGL(k_sddmm<2>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
+                       A.col_idx, q, a, t, ld, colw, G, accumulate ? 1 : 0);
+  else if (q <= 256)
+    hipLaunchKernelGGL(k_sddmm<4>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
+                       A.col_idx, q, a, t, ld, colw, G, accumulate ? 1 : 0);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t spring_chain(const Bsr& A, const int32_t* transpose, const double* H,
+                        const double* masses, const double* G, int64_t P, const int64_t* pairs,
+                        const double* unit, double* dk, double* dm, int* err, hipStream_t s) {
+  if (P > 0)
+    hipLaunchKernelGGL(k_spring_dk, dim3(nb(P, 256)), dim3(256), 0, s, P, (int)A.n_atoms, A.row_ptr, A.col_idx,
+                       masses, G, pairs, unit, dk, err);
+  if (A.n_atoms > 0)
+    hipLaunchKernelGGL(k_spring_dm, dim3(nb(A.n_atoms, 256)), dim3(256), 0, s, (int)A.n_atoms,
+                       A.row_ptr, transpose, H, masses, G, dm);
+  return hipGetLastError();
+}
+
+}  // namespace pfe

@@ -1,0 +1,787 @@
+// Dense kernels around the filter for gfx950: Gram and tall-skinny products
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64), CholQR's small Cholesky
+// factor and its inverse, the Rayleigh-Ritz eigensolve of the projected
+// matrix (parallel cyclic Jacobi), residual and column norms, casts, a
+// counter-based Gaussian generator and small Lanczos helpers.  All
+// reductions are two-pass and in a fixed order (no floating-point atomics),
+// so repeated runs are bitwise identical.
+#include "internal.h"
+
+namespace pfe {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// D(16x16) += A(16x4) B(4x16).  Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator element r of lane l is D[l/16 + 4r][l%16].
+__device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------ Gram
+// Each work-group owns a 64x64 tile of G and a contiguous range of rows;
+// rows are staged 16 at a time through LDS.  Partial tiles go to
+// work[split][q1][q2] and are summed in split order by k_gram_reduce.
+constexpr int kGramRows = 16;
+
+__global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int q1, int q2,
+                                                      const double* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ B, int64_t ldb,
+                                                      int64_t rows_per_split,
+                                                      double* __restrict__ work) {
+  __shared__ double sA[kGramRows][64 + 1];
+  __shared__ double sB[kGramRows][64 + 1];
+  const int tiles_n = (q2 + 63) / 64;
+  const int tm = blockIdx.y / tiles_n, tn = blockIdx.y % tiles_n;
+  const int m0 = tm * 64, n0 = tn * 64;
+  const int split = blockIdx.x;
+  const int64_t r_begin = (int64_t)split * rows_per_split;
+  int64_t r_end = r_begin + rows_per_split;
+  if (r_end > n) r_end = n;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  d4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4(0.0);
+
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGramRows) {
+    // stage: 16 rows x 64 cols of A and of B; thread -> (row tid/16, 4 cols)
+    {
+      const int rr = tid >> 4, cc = (tid & 15) * 4;
+      const int64_t r = r0 + rr;
+      for (int t = 0; t < 4; ++t) {
+        const int ca = m0 + cc + t, cb = n0 + cc + t;
+        sA[rr][cc + t] = (r < r_end && ca < q1) ? A[r * lda + ca] : 0.0;
+        sB[rr][cc + t] = (r < r_end && cb < q2) ? B[r * ldb + cb] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGramRows; kk += 4) {
+      const int k = kk + (lane >> 4);
+      const double a0 = sA[k][wm + (lane & 15)];
+      const double a1 = sA[k][wm + 16 + (lane & 15)];
+      const double b0 = sB[k][wn + (lane & 15)];
+      const double b1 = sB[k][wn + 16 + (lane & 15)];
+      acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
+      acc[0][1] = mfma16x16x4(a0, b1, acc[0][1]);
+      acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
+      acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+  double* out = work + (int64_t)split * q1 * q2;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row < q1 && col < q2) out[(int64_t)row * q2 + col] = acc[i][j][r];
+      }
+}
+
+__global__ void k_gram_reduce(int nsplit, int64_t count, const double* __restrict__ work,
+                              double* __restrict__ G) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double s = 0.0;
+  for (int p = 0; p < nsplit; ++p) s += work[(int64_t)p * count + i];
+  G[i] = s;
+}
+
+int gram_splits(int64_t n, int q1, int q2) {
+  const int tiles = ((q1 + 63) / 64) * ((q2 + 63) / 64);
+  int64_t want = 1024 / tiles;                     // ~1024 work-groups in total
+  if (want < 8) want = 8;
+  const int64_t maxs = (n + 255) / 256;            // at least 256 rows per split
+  if (want > maxs) want = maxs;
+  if (want < 1) want = 1;
+  return (int)want;
+}
+
+// ------------------------------------------------------------ tall GEMM
+// C[r][:q2] = A[r][:q1] Bm.  A work-group stages RB full rows of A in LDS
+// (so C may overwrite A), then produces 64-column output tiles.  RB = 32:
+// waves are 2 (16 rows) x 2 (32 columns); RB = 16 (wide q1, LDS <= 64 KB):
+// waves are 1 x 4 (16 columns each).  B fragments come from global memory
+// (q1 x q2 is small and L2-resident).
+template <int RB>
+__global__ __launch_bounds__(256) void k_gemm_tall(int64_t n, int q1, int q2,
+                                                   const double* A, int64_t lda,
+                                                   const double* __restrict__ Bm, double* C,
+                                                   int64_t ldc) {
+  extern __shared__ double sA[];   // [RB][q1p]
+  const int q1p = ((q1 + 3) / 4) * 4 + 1;
+  const int64_t r0 = (int64_t)blockIdx.x * RB;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < RB * q1p; idx += 256) {
+    const int rr = idx / q1p, c = idx % q1p;
+    const int64_t r = r0 + rr;
+    sA[idx] = (r < n && c < q1) ? A[r * lda + c] : 0.0;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  constexpr int kTiles = (RB == 32) ? 2 : 1;            // 16-column MFMA tiles per wave
+  const int wr = (RB == 32) ? (wave >> 1) * 16 : 0;
+  const int wc = (RB == 32) ? (wave & 1) * 32 : wave * 16;
+  const int kq = (q1 + 3) / 4;
+  for (int n0 = 0; n0 < q2; n0 += 64) {
+    d4 acc[kTiles];
+    int cc[kTiles];
+#pragma unroll
+    for (int t = 0; t < kTiles; ++t) {
+      acc[t] = d4(0.0);
+      cc[t] = n0 + wc + 16 * t + (lane & 15);
+    }
+    for (int kb = 0; kb < kq; ++kb) {
+      const int k = kb * 4 + (lane >> 4);
+      const double a = sA[(wr + (lane & 15)) * q1p + k];
+#pragma unroll
+      for (int t = 0; t < kTiles; ++t) {
+        const double b = (k < q1 && cc[t] < q2) ? Bm[(int64_t)k * q2 + cc[t]] : 0.0;
+        acc[t] = mfma16x16x4(a, b, acc[t]);
+      }
+    }
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + wr + (lane >> 4) + 4 * r;
+      if (row < n) {
+#pragma unroll
+        for (int t = 0; t < kTiles; ++t)
+          if (cc[t] < q2) C[row * ldc + cc[t]] = acc[t][r];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------ Cholesky and inverse
+// Single work-group.  R (upper) is formed in place in Rinv's buffer by a
+// right-looking factorisation, then inverted column by column into work
+// that is copied back.  info[0] = 0 or the failing pivot + 1.
+__global__ __launch_bounds__(1024) void k_chol_inv(int q, const double* __restrict__ G,
+                                                   double shift, double* R, double* Z,
+                                                   int* info, double* diag_max) {
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) {
+    bad = 0;
+    double mx = 0.0;
+    for (int i = 0; i < q; ++i) mx = fmax(mx, G[i * q + i]);
+    if (diag_max) diag_max[0] = mx;
+  }
+  for (int idx = tid; idx < q * q; idx += nt) {
+    const int i = idx / q, j = idx % q;
+    R[idx] = (j >= i) ? G[idx] + (i == j ? shift : 0.0) : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < q; ++k) {
+    if (tid == 0) {
+      const double d = R[k * q + k];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = k + 1;
+      } else {
+        R[k * q + k] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    const double rkk = R[k * q + k];
+    for (int j = k + 1 + tid; j < q; j += nt) R[k * q + j] /= rkk;
+    __syncthreads();
+    const int m = q - k - 1;   // trailing upper triangle of size m
+    for (int idx = tid; idx < m * m; idx += nt) {
+      const int i = k + 1 + idx / m, j = k + 1 + idx % m;
+      if (j >= i) R[i * q + j] -= R[k * q + i] * R[k * q + j];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) info[0] = bad;
+    return;
+  }
+  // Z = R^{-1} (upper): column j by back substitution
+  for (int j = tid; j < q; j += nt) {
+    for (int i = q - 1; i >= 0; --i) {
+      if (i > j) {
+        Z[i * q + j] = 0.0;
+        continue;
+      }
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int k = i + 1; k <= j; ++k) s -= R[i * q + k] * Z[k * q + j];
+      Z[i * q + j] = s / R[i * q + i];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < q * q; idx += nt) R[idx] = Z[idx];
+  if (tid == 0) info[0] = 0;
+}
+
+// ------------------------------------------------------- Jacobi eigensolve
+// One work-group, A and V in global scratch.  Round-robin (circle method)
+// ordering: m/2 disjoint rotations per step, m-1 steps per sweep.  A
+// rotation is skipped when |a_pq| <= eps sqrt(|a_pp a_qq|) or below an
+// absolute floor 1e-18 ||A||_F; sweeps stop when none is applied.
+__device__ __forceinline__ void rr_pair(int m, int step, int k, int* p, int* q) {
+  if (k == 0) {
+    *p = m - 1;
+    *q = step;
+  } else {
+    *p = (step + k) % (m - 1);
+    *q = (step - k + (m - 1)) % (m - 1);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi(int q, const double* __restrict__ S,
+                                                 double* A, double* V, double* evals, double* Q,
+                                                 int* info) {
+  __shared__ double cs[512], sn[512];
+  __shared__ int pp[512], qq[512];
+  __shared__ int rotated;
+  __shared__ double red[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int m = q + (q & 1);
+  const int half = m / 2;
+  double loc = 0.0;
+  for (int idx = tid; idx < q * q; idx += nt) {
+    const int i = idx / q, j = idx % q;
+    const double a = 0.5 * (S[i * q + j] + S[j * q + i]);
+    A[idx] = a;
+    V[idx] = (i == j) ? 1.0 : 0.0;
+    loc += a * a;
+  }
+  red[tid] = loc;
+  __syncthreads();
+  for (int s = nt / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double floor_abs = 1e-18 * sqrt(red[0]) + 1e-300;
+  const double eps = 2.220446049250313e-16;
+  int sweep = 0;
+  const int max_sweeps = 60;
+  bool converged = (q < 2);
+  for (; sweep < max_sweeps && !converged; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int step = 0; step < m - 1; ++step) {
+      if (tid < half) {
+        int p, r;
+        rr_pair(m, step, tid, &p, &r);
+        double c = 1.0, s = 0.0;
+        if (p < q && r < q) {
+          const double apq = A[p * q + r];
+          const double app = A[p * q + p], arr = A[r * q + r];
+          if (fabs(apq) > floor_abs && fabs(apq) > eps * sqrt(fabs(app * arr))) {
+            const double theta = (arr - app) / (2.0 * apq);
+            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+            rotated = 1;
+          }
+        }
+        cs[tid] = c;
+        sn[tid] = s;
+        pp[tid] = p;
+        qq[tid] = r;
+      }
+      __syncthreads();
+      // rows p, r of A
+      for (int idx = tid; idx < half * q; idx += nt) {
+        const int k = idx / q, j = idx % q;
+        const double s = sn[k];
+        if (s == 0.0) continue;
+        const double c = cs[k];
+        const int p = pp[k], r = qq[k];
+        const double a = A[p * q + j], b = A[r * q + j];
+        A[p * q + j] = c * a - s * b;
+        A[r * q + j] = s * a + c * b;
+      }
+      __syncthreads();
+      // columns p, r of A and V
+      for (int idx = tid; idx < half * q; idx += nt) {
+        const int k = idx / q, i = idx % q;
+        const double s = sn[k];
+        if (s == 0.0) continue;
+        const double c = cs[k];
+        const int p = pp[k], r = qq[k];
+        const double a = A[i * q + p], b = A[i * q + r];
+        A[i * q + p] = c * a - s * b;
+        A[i * q + r] = s * a + c * b;
+        const double va = V[i * q + p], vb = V[i * q + r];
+        V[i * q + p] = c * va - s * vb;
+        V[i * q + r] = s * va + c * vb;
+      }
+      __syncthreads();
+      // the rotated pair's off-diagonal entry is zero by construction
+      if (tid < half && sn[tid] != 0.0) {
+        A[pp[tid] * q + qq[tid]] = 0.0;
+        A[qq[tid] * q + pp[tid]] = 0.0;
+      }
+      __syncthreads();
+    }
+    converged = (rotated == 0);
+    __syncthreads();
+  }
+  // sort ascending (rank with index tie-break)
+  for (int i = tid; i < q; i += nt) {
+    const double di = A[i * q + i];
+    int rank = 0;
+    for (int j = 0; j < q; ++j) {
+      const double dj = A[j * q + j];
+      if (dj < di || (dj == di && j < i)) ++rank;
+    }
+    evals[rank] = di;
+    for (int r = 0; r < q; ++r) Q[r * q + rank] = V[r * q + i];
+  }
+  if (tid == 0) info[0] = converged ? sweep : -sweep;
+}
+
+// ------------------------------------------------------- column reductions
+constexpr int kColRows = 512;   // rows per partial block
+
+__global__ __launch_bounds__(64) void k_col_partial(int64_t n, int q, const double* __restrict__ W,
+                                                    const double* __restrict__ X, int64_t ld,
+                                                    const double* __restrict__ theta,
+                                                    double* __restrict__ part) {
+  const int64_t r0 = (int64_t)blockIdx.x * kColRows;
+  int64_t r1 = r0 + kColRows;
+  if (r1 > n) r1 = n;
+  for (int j = threadIdx.x; j < q; j += 64) {
+    const double th = theta ? theta[j] : 0.0;
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+      double v = W[r * ld + j];
+      if (X) v -= th * X[r * ld + j];
+      s += v * v;
+    }
+    part[(int64_t)blockIdx.x * q + j] = s;
+  }
+}
+
+__global__ void k_col_final(int nblk, int q, const double* __restrict__ part, double scale,
+                            double* __restrict__ res) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= q) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * q + j];
+  res[j] = sqrt(s) * scale;
+}
+
+__global__ __launch_bounds__(64) void k_coldot_partial(int64_t n, int q,
+                                                       const double* __restrict__ X,
+                                                       const double* __restrict__ Y, int64_t ld,
+                                                       double* __restrict__ part) {
+  const int64_t r0 = (int64_t)blockIdx.x * kColRows;
+  int64_t r1 = r0 + kColRows;
+  if (r1 > n) r1 = n;
+  for (int j = threadIdx.x; j < q; j += 64) {
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) s += X[r * ld + j] * Y[r * ld + j];
+    part[(int64_t)blockIdx.x * q + j] = s;
+  }
+}
+__global__ void k_colsum_final(int nblk, int q, const double* __restrict__ part,
+                               double* __restrict__ res) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= q) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * q + j];
+  res[j] = s;
+}
+__global__ void k_col_scale_inv(int64_t n, int q, double* __restrict__ X, int64_t ld,
+                                const double* __restrict__ nrm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * q) return;
+  const int64_t r = i / q, c = i % q;
+  X[r * ld + c] /= nrm[c];
+}
+
+// ------------------------------------------------------------ elementwise
+__global__ void k_cast_d2f(int64_t n, int q, const double* __restrict__ X, int64_t ldx,
+                           float* __restrict__ Y, int64_t ldy) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * q) return;
+  const int64_t r = i / q, c = i % q;
+  Y[r * ldy + c] = (float)X[r * ldx + c];
+}
+__global__ void k_cast_f2d(int64_t n, int q, const float* __restrict__ X, int64_t ldx,
+                           double* __restrict__ Y, int64_t ldy) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * q) return;
+  const int64_t r = i / q, c = i % q;
+  Y[r * ldy + c] = (double)X[r * ldx + c];
+}
+__global__ void k_copy_cols(int64_t n, int q, const double* __restrict__ X, int64_t ldx,
+                            double* __restrict__ Y, int64_t ldy) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * q) return;
+  const int64_t r = i / q, c = i % q;
+  Y[r * ldy + c] = X[r * ldx + c];
+}
+template <typename T>
+__global__ void k_zero(T* p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = T(0);
+}
+__global__ void k_scale(int64_t count, double a, double* p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] *= a;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011): 10 rounds of the Philox S-box on a 128-bit
+// counter with a 64-bit key bumped by the Weyl constants.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)M0 * c[0];
+    const uint64_t p1 = (uint64_t)M1 * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+__global__ void k_gauss(int64_t n, int q, double* __restrict__ X, int64_t ld, uint64_t seed) {
+  const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = n * q;
+  if (2 * pair >= total) return;
+  uint32_t c[4] = {(uint32_t)pair, (uint32_t)((uint64_t)pair >> 32), 0u, 0u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double two53 = 1.0 / 9007199254740992.0;
+  const uint64_t a = (((uint64_t)c[0] << 32) | c[1]) >> 11;
+  const uint64_t b = (((uint64_t)c[2] << 32) | c[3]) >> 11;
+  const double u1 = ((double)a + 0.5) * two53, u2 = ((double)b + 0.5) * two53;
+  const double rad = sqrt(-2.0 * log(u1));
+  const double ang = 6.283185307179586 * u2;
+  const double z[2] = {rad * cos(ang), rad * sin(ang)};
+  for (int t = 0; t < 2; ++t) {
+    const int64_t e = 2 * pair + t;
+    if (e < total) X[(e / q) * ld + (e % q)] = z[t];
+  }
+}
+
+// sign fix: partial argmax of |X[:, sel[s]]| per block, then per column
+__global__ __launch_bounds__(256) void k_absmax_partial(int64_t n, const double* __restrict__ X,
+                                                        int64_t ld, const int* __restrict__ sel,
+                                                        double* __restrict__ pval,
+                                                        int64_t* __restrict__ pidx) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  const int s = blockIdx.y;
+  const int col = sel[s];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  int64_t r1 = r0 + chunk;
+  if (r1 > n) r1 = n;
+  double bv = -1.0;
+  int64_t bi = -1;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    const double v = fabs(X[r * ld + col]);
+    if (v > bv) {
+      bv = v;
+      bi = r;
+    }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      const double ov = sv[threadIdx.x + st];
+      const int64_t oi = si[threadIdx.x + st];
+      if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi >= 0 && (si[threadIdx.x] < 0 || oi < si[threadIdx.x]))) {
+        sv[threadIdx.x] = ov;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pval[(int64_t)s * gridDim.x + blockIdx.x] = sv[0];
+    pidx[(int64_t)s * gridDim.x + blockIdx.x] = si[0];
+  }
+}
+
+__global__ void k_sign_final(int nsel, int nblk, const double* __restrict__ X, int64_t ld,
+                             const int* __restrict__ sel, const double* __restrict__ pval,
+                             const int64_t* __restrict__ pidx, double* __restrict__ sign) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsel) return;
+  double bv = -1.0;
+  int64_t bi = -1;
+  for (int b = 0; b < nblk; ++b) {
+    const double v = pval[(int64_t)s * nblk + b];
+    const int64_t i = pidx[(int64_t)s * nblk + b];
+    if (i >= 0 && (v > bv || (v == bv && i < bi))) {
+      bv = v;
+      bi = i;
+    }
+  }
+  sign[s] = (bi >= 0 && X[bi * ld + sel[s]] < 0.0) ? -1.0 : 1.0;
+}
+
+__global__ void k_gather_t(int64_t n, int nsel, const double* __restrict__ X, int64_t ld,
+                           const int* __restrict__ sel, const double* __restrict__ sign,
+                           double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (r >= n) return;
+  out[(int64_t)s * n + r] = X[r * ld + sel[s]] * sign[s];
+}
+
+__global__ void k_transpose_rows(int64_t m, int64_t n, const double* __restrict__ in,
+                                 double* __restrict__ out, int64_t ld) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= n) return;
+  out[r * ld + c] = in[c * n + r];
+}
+
+// ------------------------------------------------------------- Lanczos
+constexpr int kDotBlocks = 256;
+__global__ __launch_bounds__(256) void k_multidot_partial(int64_t n, int m,
+                                                          const double* __restrict__ V,
+                                                          const double* __restrict__ w,
+                                                          double* __restrict__ part) {
+  __shared__ double red[256];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  int64_t r1 = r0 + chunk;
+  if (r1 > n) r1 = n;
+  for (int j = 0; j < m; ++j) {
+    double s = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) s += V[(int64_t)j * n + r] * w[r];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * m + j] = red[0];
+    __syncthreads();
+  }
+}
+__global__ void k_multidot_final(int nblk, int m, const double* __restrict__ part,
+                                 double* __restrict__ h) {
+  const int j = threadIdx.x;
+  if (j >= m) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * m + j];
+  h[j] = s;
+}
+__global__ void k_multi_axpy(int64_t n, int m, const double* __restrict__ V,
+                             const double* __restrict__ h, double* __restrict__ w) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = w[r];
+  for (int j = 0; j < m; ++j) s -= h[j] * V[(int64_t)j * n + r];
+  w[r] = s;
+}
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
+                        double* __restrict__ y) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) y[r] = a * x[r] + b * y[r];
+}
+__global__ void k_scale_by_inv(int64_t n, const double* __restrict__ x,
+                               const double* __restrict__ nrm, double* __restrict__ y) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) y[r] = x[r] / nrm[0];
+}
+
+}  // namespace
+
+// ================================================================ launchers
+size_t gram_work_bytes(int64_t n, int q1, int q2) {
+  return (size_t)gram_splits(n, q1, q2) * q1 * q2 * sizeof(double);
+}
+
+hipError_t gram_f64(int64_t n, int q1, int q2, const double* A, int64_t lda, const double* B,
+                    int64_t ldb, double* G, void* work, hipStream_t s) {
+  if (q1 == 0 || q2 == 0) return hipSuccess;
+  const int nsplit = gram_splits(n, q1, q2);
+  int64_t rows = (n + nsplit - 1) / nsplit;
+  rows = ((rows + kGramRows - 1) / kGramRows) * kGramRows;
+  const int tiles = ((q1 + 63) / 64) * ((q2 + 63) / 64);
+  double* w = static_cast<double*>(work);
+  hipLaunchKernelGGL(k_gram_partial, dim3(nsplit, tiles), dim3(256), 0, s, n, q1, q2, A, lda, B,
+                     ldb, rows, w);
+  const int64_t count = (int64_t)q1 * q2;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks(count, 256)), dim3(256), 0, s, nsplit, count, w,
+                     G);
+  return hipGetLastError();
+}
+
+hipError_t gemm_tall_f64(int64_t n, int q1, int q2, const double* A, int64_t lda,
+                         const double* Bm, double* C, int64_t ldc, hipStream_t s) {
+  if (n == 0 || q2 == 0) return hipSuccess;
+  const int q1p = ((q1 + 3) / 4) * 4 + 1;
+  if ((size_t)32 * q1p * sizeof(double) <= 65536) {
+    hipLaunchKernelGGL(k_gemm_tall<32>, dim3(nblocks(n, 32)), dim3(256),
+                       (size_t)32 * q1p * sizeof(double), s, n, q1, q2, A, lda, Bm, C, ldc);
+  } else if ((size_t)16 * q1p * sizeof(double) <= 65536) {
+    hipLaunchKernelGGL(k_gemm_tall<16>, dim3(nblocks(n, 16)), dim3(256),
+                       (size_t)16 * q1p * sizeof(double), s, n, q1, q2, A, lda, Bm, C, ldc);
+  } else {
+    return hipErrorInvalidValue;   // q1 > 511
+  }
+  return hipGetLastError();
+}
+
+hipError_t chol_inv_f64(int q, const double* G, double shift, double* Rinv, int* info,
+                        double* diag_max, hipStream_t s) {
+  // Rinv doubles as R during the factorisation; the inverse is built in the
+  // second half of the same allocation (caller provides 2 q^2 doubles).
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, s, q, G, shift, Rinv, Rinv + (int64_t)q * q,
+                     info, diag_max);
+  return hipGetLastError();
+}
+
+size_t jacobi_work_bytes(int q) { return (size_t)2 * q * q * sizeof(double); }
+
+hipError_t sym_eig_f64(int q, const double* S, double* evals, double* Q, void* work, int* info,
+                       hipStream_t s) {
+  if (q > 1024) return hipErrorInvalidValue;
+  double* A = static_cast<double*>(work);
+  double* V = A + (int64_t)q * q;
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, q, S, A, V, evals, Q, info);
+  return hipGetLastError();
+}
+
+size_t colnorm_work_bytes(int64_t n, int q) {
+  return (size_t)nblocks(n, kColRows) * q * sizeof(double);
+}
+
+hipError_t resid_norms_f64(int64_t n, int q, const double* W, const double* X, int64_t ld,
+                           const double* theta, double inv_scale, double* res, void* work,
+                           hipStream_t s) {
+  const unsigned nb = nblocks(n, kColRows);
+  double* part = static_cast<double*>(work);
+  hipLaunchKernelGGL(k_col_partial, dim3(nb), dim3(64), 0, s, n, q, W, X, ld, theta, part);
+  hipLaunchKernelGGL(k_col_final, dim3(nblocks(q, 256)), dim3(256), 0, s, (int)nb, q, part,
+                     inv_scale, res);
+  return hipGetLastError();
+}
+
+hipError_t col_norms_f64(int64_t n, int q, const double* X, int64_t ld, double* res, void* work,
+                         hipStream_t s) {
+  return resid_norms_f64(n, q, X, nullptr, ld, nullptr, 1.0, res, work, s);
+}
+
+hipError_t col_dots_f64(int64_t n, int q, const double* X, const double* Y, int64_t ld,
+                        double* res, void* work, hipStream_t s) {
+  const unsigned nb = nblocks(n, kColRows);
+  double* part = static_cast<double*>(work);
+  hipLaunchKernelGGL(k_coldot_partial, dim3(nb), dim3(64), 0, s, n, q, X, Y, ld, part);
+  hipLaunchKernelGGL(k_colsum_final, dim3(nblocks(q, 256)), dim3(256), 0, s, (int)nb, q, part,
+                     res);
+  return hipGetLastError();
+}
+hipError_t col_scale_inv_f64(int64_t n, int q, double* X, int64_t ld, const double* nrm,
+                             hipStream_t s) {
+  if (n * q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col_scale_inv, dim3(nblocks(n * q, 256)), dim3(256), 0, s, n, q, X, ld,
+                     nrm);
+  return hipGetLastError();
+}
+hipError_t cast_f64_to_f32(int64_t n, int q, const double* X, int64_t ldx, float* Y, int64_t ldy,
+                           hipStream_t s) {
+  if (n * q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_d2f, dim3(nblocks(n * q, 256)), dim3(256), 0, s, n, q, X, ldx, Y, ldy);
+  return hipGetLastError();
+}
+hipError_t cast_f32_to_f64(int64_t n, int q, const float* X, int64_t ldx, double* Y, int64_t ldy,
+                           hipStream_t s) {
+  if (n * q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_f2d, dim3(nblocks(n * q, 256)), dim3(256), 0, s, n, q, X, ldx, Y, ldy);
+  return hipGetLastError();
+}
+hipError_t copy_cols_f64(int64_t n, int q, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                         hipStream_t s) {
+  if (n * q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_cols, dim3(nblocks(n * q, 256)), dim3(256), 0, s, n, q, X, ldx, Y, ldy);
+  return hipGetLastError();
+}
+hipError_t zero_f64(double* p, int64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero<double>, dim3(nblocks(count, 256)), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+hipError_t zero_f32(float* p, int64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero<float>, dim3(nblocks(count, 256)), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+hipError_t scale_f64(int64_t count, double a, double* p, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3(nblocks(count, 256)), dim3(256), 0, s, count, a, p);
+  return hipGetLastError();
+}
+hipError_t gaussian_fill_f64(int64_t n, int q, double* X, int64_t ld, uint64_t seed, hipStream_t s) {
+  const int64_t pairs = (n * q + 1) / 2;
+  if (pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gauss, dim3(nblocks(pairs, 256)), dim3(256), 0, s, n, q, X, ld, seed);
+  return hipGetLastError();
+}
+
+hipError_t gather_transpose_signfix(int64_t n, int nsel, const double* X, int64_t ld,
+                                    const int* sel, double* out, void* work, hipStream_t s) {
+  if (nsel == 0 || n == 0) return hipSuccess;
+  const int nblk = 64;
+  double* pval = static_cast<double*>(work);
+  int64_t* pidx = reinterpret_cast<int64_t*>(pval + (int64_t)nsel * nblk);
+  double* sign = reinterpret_cast<double*>(pidx + (int64_t)nsel * nblk);
+  hipLaunchKernelGGL(k_absmax_partial, dim3(nblk, nsel), dim3(256), 0, s, n, X, ld, sel, pval,
+                     pidx);
+  hipLaunchKernelGGL(k_sign_final, dim3(nblocks(nsel, 64)), dim3(64), 0, s, nsel, nblk, X, ld, sel,
+                     pval, pidx, sign);
+  hipLaunchKernelGGL(k_gather_t, dim3(nblocks(n, 256), nsel), dim3(256), 0, s, n, nsel, X, ld, sel,
+                     sign, out);
+  return hipGetLastError();
+}
+
+hipError_t transpose_to_rows(int64_t m, int64_t n, const double* in, double* out, int64_t ld,
+                             hipStream_t s) {
+  if (m == 0 || n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_rows, dim3(nblocks(n, 256), (unsigned)m), dim3(256), 0, s, m, n,
+                     in, out, ld);
+  return hipGetLastError();
+}
+
+size_t multidot_work_bytes(int64_t n, int m) { return (size_t)kDotBlocks * m * sizeof(double); }
+
+hipError_t multi_dot_f64(int64_t n, int m, const double* V, const double* w, double* h,
+                         void* work, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  double* part = static_cast<double*>(work);
+  hipLaunchKernelGGL(k_multidot_partial, dim3(kDotBlocks), dim3(256), 0, s, n, m, V, w, part);
+  hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(1024), 0, s, kDotBlocks, m, part, h);
+  return hipGetLastError();
+}
+hipError_t multi_axpy_f64(int64_t n, int m, const double* V, const double* h, double* w,
+                          hipStream_t s) {
+  if (m == 0 || n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_multi_axpy, dim3(nblocks(n, 256)), dim3(256), 0, s, n, m, V, h, w);
+  return hipGetLastError();
+}
+hipError_t axpby_f64(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby, dim3(nblocks(n, 256)), dim3(256), 0, s, n, a, x, b, y);
+  return hipGetLastError();
+}
+hipError_t scale_by_inv_f64(int64_t n, const double* x, const double* nrm, double* y,
+                            hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_by_inv, dim3(nblocks(n, 256)), dim3(256), 0, s, n, x, nrm, y);
+  return hipGetLastError();
+}
+
+}  // namespace pfe

@@ -1,0 +1,478 @@
+// Block-sparse (3x3 BSR) kernels for gfx950: the fused Chebyshev step of
+// Algorithm 2 (three-term recurrence, eq. 3-term-recurrence, with the
+// spectral map of eq. transf.1 folded into scalars), the single-vector SpMV
+// used by the Lanczos bounds, mass weighting (eq. intro.2) and validation.
+//
+// Mapping of the fused step: one wavefront per atom row i (three matrix rows).
+// Lane l owns NP column chunks of VW contiguous elements, chunk = l + 64 p,
+// so a neighbour's three rows of T_in (3 q contiguous elements) are read by
+// coalesced 16-32 byte vector loads.  The row index, the block-column index
+// and the nine block values are wave-uniform and go through scalar loads.
+// Work-groups are remapped so that every XCD walks a contiguous range of
+// atom rows (neighbouring rows share T_in rows in that XCD's L2).
+#include "internal.h"
+
+namespace pfe {
+namespace {
+
+template <typename T, int N>
+struct VT {
+  typedef T type __attribute__((ext_vector_type(N)));
+};
+template <typename T>
+struct VT<T, 1> {
+  typedef T type;
+};
+
+#ifndef PFE_CHEB_XCD_REMAP
+#define PFE_CHEB_XCD_REMAP 1   // each XCD walks a contiguous range of rows
+#endif
+#ifndef PFE_CHEB_NT_OUT
+#define PFE_CHEB_NT_OUT 1       // T_out written with the nontemporal hint
+#endif
+constexpr int kWavesPerBlock = 4;
+#ifndef PFE_CHEB_UNROLL
+#define PFE_CHEB_UNROLL 8
+#endif
+constexpr int kUnroll = PFE_CHEB_UNROLL;
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <typename V>
+__device__ __forceinline__ V ld_nt(const V* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename V>
+__device__ __forceinline__ void st_nt(V v, V* p) {
+  __builtin_nontemporal_store(v, p);
+}
+
+// Epilogue shared by both variants: out = alpha acc + beta tin + delta prev,
+// y = y_keep y + gam_out out + gam_in tin.
+template <typename T, int VW, int NP>
+__device__ __forceinline__ void cheb_epilogue(typename VT<T, VW>::type (&acc)[3][NP],
+                                              const bool (&act)[NP], int row, int lane, int col0,
+                                              const T* __restrict__ tin, const T* prev, T* out,
+                                              T* y, int64_t ld, T alpha, T beta, T delta,
+                                              T y_keep, T gam_out, T gam_in) {
+  using vt = typename VT<T, VW>::type;
+  const bool need_tin = (beta != T(0)) || (y != nullptr && gam_in != T(0));
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    if (!act[p]) continue;
+    const int c = (lane + 64 * p) * VW;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int64_t off = (int64_t)(3 * row + a) * ld + col0 + c;
+      vt o = alpha * acc[a][p];
+      vt ti = vt(0);
+      if (need_tin) {
+        ti = *reinterpret_cast<const vt*>(tin + off);
+        o += beta * ti;
+      }
+      if (delta != T(0)) o += delta * ld_nt(reinterpret_cast<const vt*>(prev + off));
+      if (PFE_CHEB_NT_OUT)
+        st_nt(o, reinterpret_cast<vt*>(out + off));
+      else
+        *reinterpret_cast<vt*>(out + off) = o;
+      if (y != nullptr) {
+        vt yv = gam_out * o + gam_in * ti;
+        if (y_keep != T(0)) yv += y_keep * ld_nt(reinterpret_cast<const vt*>(y + off));
+        st_nt(yv, reinterpret_cast<vt*>(y + off));
+      }
+    }
+  }
+}
+
+// Variant S: indices and block values through the scalar unit.
+template <typename T, int VW, int NP, int U>
+__global__ __launch_bounds__(256) void k_cheb_step(
+    int n_atoms, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+    const T* __restrict__ vals, const T* __restrict__ tin, const T* prev, T* out, T* y, int q,
+    int64_t ld, T alpha, T beta, T delta, T y_keep, T gam_out, T gam_in, int per_xcd) {
+  using vt = typename VT<T, VW>::type;
+  const int b = blockIdx.x;
+  const int lb = PFE_CHEB_XCD_REMAP ? (b & 7) * per_xcd + (b >> 3) : b;
+  const int wave = uniform(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int row = uniform(lb * kWavesPerBlock + wave);
+  if (row >= n_atoms) return;
+  const int col0 = blockIdx.y * (64 * NP * VW);
+
+  vt acc[3][NP];
+  bool act[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    acc[0][p] = vt(0);
+    acc[1][p] = vt(0);
+    acc[2][p] = vt(0);
+    act[p] = col0 + (lane + 64 * p) * VW < q;
+  }
+  const int64_t b0 = row_ptr[row];
+  const int64_t b1 = row_ptr[row + 1];
+  // col_idx and vals are padded by kBsrPad entries on the device, so the U
+  // index and value loads of a group are unconditional; lanes of neighbours
+  // past the row end read zeros instead of T_in.
+  for (int64_t k = b0; k < b1; k += U) {
+    vt x[U][3][NP];
+    int j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = col_idx[k + u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool valid = (u == 0) || (k + u < b1);
+      const T* src = tin + (int64_t)(3 * (valid ? j[u] : row)) * ld + col0;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int c = (lane + 64 * p) * VW;
+        if (act[p] && valid) {
+          x[u][0][p] = *reinterpret_cast<const vt*>(src + c);
+          x[u][1][p] = *reinterpret_cast<const vt*>(src + ld + c);
+          x[u][2][p] = *reinterpret_cast<const vt*>(src + 2 * ld + c);
+        } else {
+          x[u][0][p] = vt(0);
+          x[u][1][p] = vt(0);
+          x[u][2][p] = vt(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T* hv = vals + (k + u) * 9;
+      T h[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) h[t] = hv[t];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        acc[0][p] += h[0] * x[u][0][p] + h[1] * x[u][1][p] + h[2] * x[u][2][p];
+        acc[1][p] += h[3] * x[u][0][p] + h[4] * x[u][1][p] + h[5] * x[u][2][p];
+        acc[2][p] += h[6] * x[u][0][p] + h[7] * x[u][1][p] + h[8] * x[u][2][p];
+      }
+    }
+  }
+  cheb_epilogue<T, VW, NP>(acc, act, row, lane, col0, tin, prev, out, y, ld, alpha, beta, delta,
+                           y_keep, gam_out, gam_in);
+}
+
+// Variant L: the work-group first stages the column indices and block values
+// of its four rows (one contiguous range of blocks) in LDS with coalesced
+// loads; each wave then takes its row's neighbours U at a time, reading the
+// indices and values as LDS broadcasts, so the only long-latency step per
+// group is the batch of T_in gathers.
+constexpr int kStageBlocks = 128;
+
+template <typename T, int VW, int NP, int U>
+__global__ __launch_bounds__(256) void k_cheb_step_lds(
+    int n_atoms, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+    const T* __restrict__ vals, const T* __restrict__ tin, const T* prev, T* out, T* y, int q,
+    int64_t ld, T alpha, T beta, T delta, T y_keep, T gam_out, T gam_in, int per_xcd) {
+  using vt = typename VT<T, VW>::type;
+  __shared__ T s_val[kStageBlocks * 9];
+  __shared__ int s_col[kStageBlocks + U];
+  const int b = blockIdx.x;
+  const int lb = PFE_CHEB_XCD_REMAP ? (b & 7) * per_xcd + (b >> 3) : b;
+  const int r0 = lb * kWavesPerBlock;
+  if (r0 >= n_atoms) return;                       // uniform over the work-group
+  const int wave = uniform(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int row = r0 + wave;
+  const bool row_ok = row < n_atoms;
+  const int r_end = min(r0 + kWavesPerBlock, n_atoms);
+  const int col0 = blockIdx.y * (64 * NP * VW);
+  const int64_t wb0 = row_ptr[r0], wb1 = row_ptr[r_end];
+  const int64_t b0 = row_ok ? row_ptr[row] : wb1;
+  const int64_t b1 = row_ok ? row_ptr[row + 1] : wb1;
+
+  vt acc[3][NP];
+  bool act[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    acc[0][p] = vt(0);
+    acc[1][p] = vt(0);
+    acc[2][p] = vt(0);
+    act[p] = col0 + (lane + 64 * p) * VW < q;
+  }
+  for (int64_t c0 = wb0; c0 < wb1; c0 += kStageBlocks) {
+    const int cnt = (int)min((int64_t)kStageBlocks, wb1 - c0);
+    __syncthreads();
+    for (int i = tid; i < cnt * 9; i += 256) s_val[i] = vals[c0 * 9 + i];
+    for (int i = tid; i < cnt + U; i += 256) s_col[i] = (i < cnt) ? col_idx[c0 + i] : 0;
+    __syncthreads();
+    const int k_lo = (int)(max(b0, c0) - c0);
+    const int k_hi = (int)(min(b1, c0 + cnt) - c0);
+    for (int k = k_lo; k < k_hi; k += U) {
+      vt x[U][3][NP];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool valid = (u == 0) || (k + u < k_hi);
+        const int j = valid ? s_col[k + u] : row;
+        const T* src = tin + (int64_t)(3 * j) * ld + col0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const int c = (lane + 64 * p) * VW;
+          if (act[p] && valid) {
+            x[u][0][p] = *reinterpret_cast<const vt*>(src + c);
+            x[u][1][p] = *reinterpret_cast<const vt*>(src + ld + c);
+            x[u][2][p] = *reinterpret_cast<const vt*>(src + 2 * ld + c);
+          } else {
+            x[u][0][p] = vt(0);
+            x[u][1][p] = vt(0);
+            x[u][2][p] = vt(0);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (u == 0 || k + u < k_hi) {
+          const T* hv = s_val + (k + u) * 9;
+          T h[9];
+#pragma unroll
+          for (int t = 0; t < 9; ++t) h[t] = hv[t];
+#pragma unroll
+          for (int p = 0; p < NP; ++p) {
+            acc[0][p] += h[0] * x[u][0][p] + h[1] * x[u][1][p] + h[2] * x[u][2][p];
+            acc[1][p] += h[3] * x[u][0][p] + h[4] * x[u][1][p] + h[5] * x[u][2][p];
+            acc[2][p] += h[6] * x[u][0][p] + h[7] * x[u][1][p] + h[8] * x[u][2][p];
+          }
+        }
+      }
+    }
+  }
+  if (!row_ok) return;
+  cheb_epilogue<T, VW, NP>(acc, act, row, lane, col0, tin, prev, out, y, ld, alpha, beta, delta,
+                           y_keep, gam_out, gam_in);
+}
+
+#ifndef PFE_CHEB_VARIANT
+#define PFE_CHEB_VARIANT 1   // 0: scalar, 1: LDS-staged
+#endif
+
+template <typename T, int VW, int NP>
+hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, T* out, T* y,
+                       int q, int64_t ld, T alpha, T beta, T delta, T y_keep, T gam_out, T gam_in,
+                       hipStream_t s) {
+  const int64_t nblk = (A.n_atoms + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int per_xcd = (int)((nblk + 7) / 8);
+  const int cols_per_group = 64 * NP * VW;
+  dim3 grid((unsigned)(per_xcd * 8), (unsigned)((q + cols_per_group - 1) / cols_per_group));
+  if (PFE_CHEB_VARIANT == 1)
+    hipLaunchKernelGGL((k_cheb_step_lds<T, VW, NP, kUnroll>), grid, dim3(256), 0, s,
+                       (int)A.n_atoms, A.row_ptr, A.col_idx, vals, tin, prev, out, y, q, ld,
+                       alpha, beta, delta, y_keep, gam_out, gam_in, per_xcd);
+  else
+    hipLaunchKernelGGL((k_cheb_step<T, VW, NP, kUnroll>), grid, dim3(256), 0, s, (int)A.n_atoms,
+                       A.row_ptr, A.col_idx, vals, tin, prev, out, y, q, ld, alpha, beta, delta,
+                       y_keep, gam_out, gam_in, per_xcd);
+  return hipGetLastError();
+}
+
+template <typename T>
+bool aligned(const void* p, int bytes) {
+  return p == nullptr || (reinterpret_cast<uintptr_t>(p) % bytes) == 0;
+}
+
+// Chooses the vector width (largest that divides q and ld with aligned
+// pointers) and the number of column passes per lane.
+template <typename T, int MAXVW>
+hipError_t dispatch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, T* out, T* y,
+                         int q, int64_t ld, T alpha, T beta, T delta, T y_keep, T gam_out,
+                         T gam_in, hipStream_t s) {
+  if (A.n_atoms == 0 || q == 0) return hipSuccess;
+  // smallest vector width that covers q with one 64-lane pass, if the
+  // layout allows it; otherwise the widest that does
+  int want = 1;
+  while (want < MAXVW && want * 64 < q) want *= 2;
+  auto fits = [&](int v) {
+    const int bytes = v * (int)sizeof(T);
+    return q % v == 0 && ld % v == 0 && aligned<T>(tin, bytes) && aligned<T>(prev, bytes) &&
+           aligned<T>(out, bytes) && aligned<T>(y, bytes);
+  };
+  int vw = want;
+  while (vw > 1 && !fits(vw)) vw /= 2;
+  const int chunks = (q + vw - 1) / vw;
+  const int np = chunks <= 64 ? 1 : (chunks <= 128 ? 2 : 4);
+#define PFE_CHEB_CASE(VW_, NP_)                                                               \
+  if (vw == VW_ && np == NP_)                                                                 \
+    return launch_cheb<T, VW_, NP_>(A, vals, tin, prev, out, y, q, ld, alpha, beta, delta,    \
+                                    y_keep, gam_out, gam_in, s);
+  PFE_CHEB_CASE(1, 1)
+  PFE_CHEB_CASE(1, 2)
+  PFE_CHEB_CASE(1, 4)
+  PFE_CHEB_CASE(2, 1)
+  PFE_CHEB_CASE(2, 2)
+  PFE_CHEB_CASE(2, 4)
+  PFE_CHEB_CASE(4, 1)
+  PFE_CHEB_CASE(4, 2)
+  PFE_CHEB_CASE(4, 4)
+  if constexpr (MAXVW >= 8) {
+    PFE_CHEB_CASE(8, 1)
+    PFE_CHEB_CASE(8, 2)
+    PFE_CHEB_CASE(8, 4)
+  }
+#undef PFE_CHEB_CASE
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ SpMV
+__global__ __launch_bounds__(256) void k_spmv(int n_atoms, const int64_t* __restrict__ row_ptr,
+                                              const int32_t* __restrict__ col_idx,
+                                              const double* __restrict__ vals,
+                                              const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_atoms) return;
+  double a0 = 0, a1 = 0, a2 = 0;
+  for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+    const int j = col_idx[k];
+    const double* h = vals + k * 9;
+    const double x0 = x[3 * (int64_t)j], x1 = x[3 * (int64_t)j + 1], x2 = x[3 * (int64_t)j + 2];
+    a0 += h[0] * x0 + h[1] * x1 + h[2] * x2;
+    a1 += h[3] * x0 + h[4] * x1 + h[5] * x2;
+    a2 += h[6] * x0 + h[7] * x1 + h[8] * x2;
+  }
+  y[3 * (int64_t)i] = a0;
+  y[3 * (int64_t)i + 1] = a1;
+  y[3 * (int64_t)i + 2] = a2;
+}
+
+// -------------------------------------------------------- weighting, casts
+__global__ void k_mass_weight(int n_atoms, const int64_t* __restrict__ row_ptr,
+                              const int32_t* __restrict__ col_idx, const double* __restrict__ K,
+                              const double* __restrict__ m, double* __restrict__ H) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_atoms) return;
+  const double mi = m[i];
+  for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+    const double w = 1.0 / sqrt(mi * m[col_idx[k]]);
+    for (int t = 0; t < 9; ++t) H[k * 9 + t] = K[k * 9 + t] * w;
+  }
+}
+
+__global__ void k_shift_scale_f32(int n_atoms, const int64_t* __restrict__ row_ptr,
+                                  const int32_t* __restrict__ col_idx,
+                                  const double* __restrict__ H, double c, double inv_e,
+                                  float* __restrict__ H32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_atoms) return;
+  for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+    const bool diag = col_idx[k] == i;
+    for (int t = 0; t < 9; ++t) {
+      double v = H[k * 9 + t];
+      if (diag && (t == 0 || t == 4 || t == 8)) v -= c;
+      H32[k * 9 + t] = (float)(v * inv_e);
+    }
+  }
+}
+
+__global__ void k_validate(int n_atoms, const int64_t* __restrict__ row_ptr,
+                           const int32_t* __restrict__ col_idx, const double* __restrict__ v,
+                           int32_t* __restrict__ transpose, int* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_atoms) return;
+  const int64_t b0 = row_ptr[i], b1 = row_ptr[i + 1];
+  int flags = 0;
+  bool has_diag = false;
+  if (b1 < b0) flags |= 1;
+  for (int64_t k = b0; k < b1; ++k) {
+    const int j = col_idx[k];
+    if (j < 0 || j >= n_atoms || (k > b0 && col_idx[k - 1] >= j)) {
+      flags |= 1;
+      continue;
+    }
+    if (j == i) has_diag = true;
+    for (int t = 0; t < 9; ++t)
+      if (!isfinite(v[k * 9 + t])) flags |= 2;
+    // transpose partner (j, i) by binary search in row j
+    int64_t lo = row_ptr[j], hi = row_ptr[j + 1] - 1, found = -1;
+    while (lo <= hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      const int cm = col_idx[mid];
+      if (cm == i) {
+        found = mid;
+        break;
+      }
+      if (cm < i)
+        lo = mid + 1;
+      else
+        hi = mid - 1;
+    }
+    if (found < 0) {
+      flags |= 4;
+      transpose[k] = -1;
+      continue;
+    }
+    transpose[k] = (int32_t)found;
+    for (int p = 0; p < 3; ++p)
+      for (int r = 0; r < 3; ++r)
+        if (v[k * 9 + p * 3 + r] != v[found * 9 + r * 3 + p]) flags |= 8;
+  }
+  if (!has_diag) flags |= 1;
+  if (flags) atomicOr(err, flags);
+}
+
+__global__ void k_validate_masses(int n, const double* __restrict__ m, int* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = m[i];
+  if (!(v > 0.0) || !isfinite(v)) atomicOr(err, 16);
+}
+
+inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t cheb_step_f64(const Bsr& A, const double* vals, const double* tin, const double* prev,
+                         double* out, double* y, int q, int64_t ld, double alpha, double beta,
+                         double delta, double y_keep, double gam_out, double gam_in,
+                         hipStream_t s) {
+  return dispatch_cheb<double, 4>(A, vals, tin, prev, out, y, q, ld, alpha, beta, delta, y_keep,
+                                  gam_out, gam_in, s);
+}
+
+hipError_t cheb_step_f32(const Bsr& A, const float* vals, const float* tin, const float* prev,
+                         float* out, float* y, int q, int64_t ld, float alpha, float beta,
+                         float delta, float y_keep, float gam_out, float gam_in, hipStream_t s) {
+  return dispatch_cheb<float, 8>(A, vals, tin, prev, out, y, q, ld, alpha, beta, delta, y_keep,
+                                 gam_out, gam_in, s);
+}
+
+hipError_t spmv_f64(const Bsr& A, const double* vals, const double* x, double* y, hipStream_t s) {
+  if (A.n_atoms == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spmv, dim3(nb(A.n_atoms, 256)), dim3(256), 0, s, (int)A.n_atoms,
+                     A.row_ptr, A.col_idx, vals, x, y);
+  return hipGetLastError();
+}
+
+hipError_t mass_weight(const Bsr& A, const double* K, const double* masses, double* H,
+                       hipStream_t s) {
+  if (A.n_atoms == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mass_weight, dim3(nb(A.n_atoms, 128)), dim3(128), 0, s, (int)A.n_atoms,
+                     A.row_ptr, A.col_idx, K, masses, H);
+  return hipGetLastError();
+}
+
+hipError_t shift_scale_to_f32(const Bsr& A, const double* H, double c, double e, float* H32,
+                              hipStream_t s) {
+  if (A.n_atoms == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shift_scale_f32, dim3(nb(A.n_atoms, 128)), dim3(128), 0, s,
+                     (int)A.n_atoms, A.row_ptr, A.col_idx, H, c, 1.0 / e, H32);
+  return hipGetLastError();
+}
+
+hipError_t validate_bsr(const Bsr& A, const double* vals, int32_t* transpose, int* err_flags,
+                        hipStream_t s) {
+  if (A.n_atoms == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate, dim3(nb(A.n_atoms, 128)), dim3(128), 0, s, (int)A.n_atoms,
+                     A.row_ptr, A.col_idx, vals, transpose, err_flags);
+  return hipGetLastError();
+}
+
+hipError_t validate_masses(int64_t n_atoms, const double* masses, int* err_flags, hipStream_t s) {
+  if (n_atoms == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate_masses, dim3(nb(n_atoms, 256)), dim3(256), 0, s, (int)n_atoms,
+                     masses, err_flags);
+  return hipGetLastError();
+}
+
+}  // namespace pfe

@@ -1,0 +1,116 @@
+"""GPU parity of the fused Chebyshev filter (Algorithm 2), the Lanczos bounds
+and the Hessian import against the CPU oracle."""
+import numpy as np
+import pytest
+
+import paper_1902_07041_amd as P
+from oracle import chebyshev, filters as F, lanczos
+from synth import gaussian_block, gaussian_vector
+
+from gpu_common import GlassCase, banner, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def case():
+    banner("glass N=1000")
+    c = GlassCase(1000)
+    c.h = c.handle()
+    c.ub = float(c.lam[-1]) * 1.01
+    P.pfe_set_bounds(c.h, 0.0, c.ub)
+    yield c
+    P.pfe_destroy(c.h)
+
+
+def design(case, d, smoothing=P.PFE_SMOOTH_NONE):
+    return P.pfe_design_filter(0.01 * case.lam[-1], 0.03 * case.lam[-1], 0.0, case.ub,
+                               degree=d, smoothing=smoothing)
+
+
+@pytest.mark.parametrize("q", [1, 3, 32, 96, 100, 160, 256, 1030])
+@pytest.mark.parametrize("d", [0, 1, 2, 3, 30])
+def test_filter_fp64_parity(case, q, d):
+    banner(f"apply_filter fp64 q={q} d={d}")
+    f = design(case, max(d, 1))
+    if d < f.degree:
+        f.coef = f.coef[: d + 1].copy()
+        f.degree = d
+    X = gaussian_block(case.n, q, 100 + q)
+    Y = P.pfe_apply_filter(case.h, f, X)
+    ref = chebyshev.apply_filter(case.H, f.c, f.e, f.coef, X)
+    assert rel_err(Y, ref) < 1e-12
+
+
+@pytest.mark.parametrize("q", [1, 8, 96, 160, 256])
+def test_filter_fp32_parity(case, q):
+    banner(f"apply_filter fp32 q={q}")
+    f = design(case, 30)
+    X = gaussian_block(case.n, q, 200 + q)
+    Y = P.pfe_apply_filter(case.h, f, X.astype(np.float32))
+    ref = chebyshev.apply_filter(case.H, f.c, f.e, f.coef, X)
+    # FP32 values/vectors: rounding ~6e-8 per operation grows with the degree
+    assert rel_err(Y, ref) < 5e-5
+
+
+def test_filter_device_pointers(case):
+    import torch
+    banner("apply_filter torch device tensors")
+    f = design(case, 20)
+    X = gaussian_block(case.n, 64, 7)
+    Xt = torch.tensor(X, device="cuda")
+    Yt = P.pfe_apply_filter(case.h, f, Xt)
+    torch.cuda.synchronize()
+    ref = chebyshev.apply_filter(case.H, f.c, f.e, f.coef, X)
+    assert rel_err(Yt.cpu().numpy(), ref) < 1e-12
+
+
+def test_bounds_parity(case):
+    banner("estimate_bounds")
+    v0 = gaussian_vector(case.n, 7)
+    lb, ub, th = P.pfe_estimate_bounds(case.h, 30, v0)
+    rlb, rub, rth = lanczos.lanczos_bounds(case.H, v0, 30)
+    assert lb == 0.0
+    assert th == pytest.approx(rth, rel=1e-12)
+    assert ub == pytest.approx(rub, rel=1e-10)
+    assert th <= case.lam[-1] * (1 + 1e-13) <= ub
+    P.pfe_set_bounds(case.h, 0.0, case.ub)
+
+
+def test_bounds_own_generator(case):
+    banner("estimate_bounds seeded")
+    lb, ub, th = P.pfe_estimate_bounds(case.h, 30, None, 5)
+    assert th <= case.lam[-1] * (1 + 1e-13) <= ub
+    assert (case.lam[-1] - th) / case.lam[-1] < 1e-3
+    P.pfe_set_bounds(case.h, 0.0, case.ub)
+
+
+def test_set_hessian_validation():
+    banner("set_hessian validation")
+    c = GlassCase(125, seed=2, dense=False)
+    h = P.pfe_create(0)
+    try:
+        g = c.g
+        bad = g.blocks.copy()
+        bad[1, 0, 1] += 1e-3                       # breaks K_ij = K_ji^T
+        with pytest.raises(P.PfeError) as e:
+            P.pfe_set_hessian(h, g.row_ptr, g.col_idx, bad, g.masses)
+        assert e.value.status == -2
+        m = g.masses.copy(); m[5] = -1.0
+        with pytest.raises(P.PfeError) as e:
+            P.pfe_set_hessian(h, g.row_ptr, g.col_idx, g.blocks, m)
+        assert e.value.status == -1
+        nanb = g.blocks.copy(); nanb[7, 2, 2] = np.nan
+        with pytest.raises(P.PfeError) as e:
+            P.pfe_set_hessian(h, g.row_ptr, g.col_idx, nanb, g.masses)
+        assert e.value.status == -1
+        ci = g.col_idx.copy(); ci[[0, 1]] = ci[[1, 0]]   # unsorted row
+        with pytest.raises(P.PfeError):
+            P.pfe_set_hessian(h, g.row_ptr, ci, g.blocks, g.masses)
+        # calls out of order
+        with pytest.raises(P.PfeError) as e:
+            P.pfe_solve_interval(h, 0.0, 1.0, 4, 4, degree=10)
+        assert e.value.status == -8
+        P.pfe_set_hessian(h, g.row_ptr, g.col_idx, g.blocks, g.masses)
+    finally:
+        P.pfe_destroy(h)

@@ -1,0 +1,92 @@
+"""GPU parity of the eigensolver (filtered subspace iteration + CholQR2 +
+Rayleigh-Ritz) against the plain definition (dense LAPACK) and the oracle's
+subspace iteration."""
+import numpy as np
+import pytest
+
+import paper_1902_07041_amd as P
+from oracle import dense, filters as F, lanczos, subspace
+from synth import gaussian_block, gaussian_vector
+
+from gpu_common import GlassCase, banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def case():
+    banner("glass N=1000 (solve)")
+    c = GlassCase(1000)
+    c.h = c.handle()
+    _, c.ub, c.th = lanczos.lanczos_bounds(c.H, gaussian_vector(c.n, 7), 30)
+    P.pfe_set_bounds(c.h, 0.0, c.ub)
+    c.lo, c.hi = 0.01 * c.th, 0.03 * c.th
+    yield c
+    P.pfe_destroy(c.h)
+
+
+def check_pairs(case, out, rel_tol, res_tol):
+    ref, V = dense.window(case.lam, case.U, case.lo, case.hi)
+    assert out["evals"].shape == ref.shape, (out["evals"], ref)
+    np.testing.assert_allclose(out["evals"], ref, rtol=rel_tol)
+    Vg = out["evecs"].T
+    # residuals recomputed on the CPU
+    r = np.linalg.norm(case.H @ Vg - Vg * out["evals"][None, :], axis=0) / case.ub
+    assert r.max() <= res_tol
+    np.testing.assert_allclose(np.linalg.norm(Vg, axis=0), 1.0, atol=1e-12)
+    # same invariant subspace
+    sv = np.linalg.svd(V.T @ Vg, compute_uv=False)
+    assert sv.min() > 1 - 1e-8
+    # sign convention: largest-magnitude entry positive
+    idx = np.argmax(np.abs(Vg), axis=0)
+    assert np.all(Vg[idx, np.arange(Vg.shape[1])] > 0)
+
+
+def test_solve_fp64_matches_dense(case):
+    banner("solve fp64 N=1000 q=32 d=80")
+    X0 = gaussian_block(case.n, 32, 11)
+    out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-10, x0=X0)
+    assert out["status"] == "PFE_OK"
+    check_pairs(case, out, 1e-10, 1e-9)
+    assert out["resid"].max() <= 1e-10
+
+
+def test_solve_fp64_matches_oracle_si(case):
+    banner("solve fp64 vs oracle SI")
+    X0 = gaussian_block(case.n, 32, 11)
+    c, e = F.spectral_map(0.0, case.ub)
+    f = P.pfe_design_filter(case.lo, case.hi, 0.0, case.ub, degree=80)
+    th, X, res, it = subspace.subspace_iteration(case.H, c, e, f.coef, X0, case.lo, case.hi,
+                                                 case.ub, tol=1e-12)
+    out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-10, x0=X0)
+    np.testing.assert_allclose(out["evals"], th, rtol=1e-10)
+
+
+def test_solve_fp32_form(case):
+    banner("solve fp32-filter form N=1000")
+    X0 = gaussian_block(case.n, 32, 11)
+    out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-9,
+                               precision=P.PFE_FP32, x0=X0)
+    assert out["status"] == "PFE_OK", out["stats"]
+    check_pairs(case, out, 1e-8, 1e-8)
+    assert out["stats"]["refined"] == 1
+
+
+def test_solve_seeded_start_and_capacity(case):
+    banner("solve seeded start / capacity")
+    out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-10, seed=3)
+    assert out["evals"].size == 12
+    with pytest.raises(P.PfeError) as e:
+        P.pfe_solve_interval(case.h, case.lo, case.hi, 5, 32, degree=80, tol=1e-10, seed=3)
+    assert e.value.status == -6
+
+
+def test_solve_bounds_too_small_is_detected(case):
+    banner("solve EBOUNDS")
+    P.pfe_set_bounds(case.h, 0.0, 0.5 * case.th)
+    try:
+        with pytest.raises(P.PfeError) as e:
+            P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-10, seed=3)
+        assert e.value.status == -7
+    finally:
+        P.pfe_set_bounds(case.h, 0.0, case.ub)

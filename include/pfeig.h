@@ -70,7 +70,8 @@ typedef enum {
  * default priority. */
 pfe_status pfe_create(int device, void* hip_stream, pfe_handle* out);
 void pfe_destroy(pfe_handle h);
-/* Message describing the last non-OK status of this handle ("" if none). */
+/* Message describing the last non-OK status of this handle ("" if none);
+ * with h == NULL, the reason the calling thread's last pfe_create failed. */
 const char* pfe_last_error(pfe_handle h);
 /* Library version string. */
 const char* pfe_version(void);
@@ -171,7 +172,8 @@ typedef struct {
   double eps;          /* filter margin in mapped units (0: by eq. thresh at degree) */
   double r;            /* eq. thresh rate; 0 -> 0.1^(1/4) */
   int32_t smoothing;   /* PFE_SMOOTH_* */
-  double tol;          /* residual ||H v - lambda v|| / lam_ub; 0 -> 1e-10 */
+  double tol;          /* residual ||H v - lambda v|| / lam_ub; 0 -> 1e-10 (FP64),
+                          1e-8 (FP32 filter form) */
   int32_t max_iter;    /* outer iterations (filter applications); 0 -> 100 */
   int32_t precision;   /* PFE_FP64, or PFE_FP32: FP32 filter with FP64
                           orthonormalisation, Rayleigh-Ritz and residuals, then
@@ -213,7 +215,7 @@ void pfe_solve_opts_default(pfe_solve_opts* opts);
  * ||H v - lambda v|| / lam_ub (host, may be NULL), stats (may be NULL).
  * Stops when every Ritz value within 1e-6 lam_ub of the window has a
  * residual <= tol in two consecutive iterations with the same in-window
- * count.  ECAPACITY: *n_found = number of in-window Ritz values (> nev),
+ * count (and at least three iterations have run).  ECAPACITY: *n_found = number of in-window Ritz values (> nev),
  * nothing else written.  ENOCONV: the converged in-window pairs are
  * returned. */
 pfe_status pfe_solve_interval(pfe_handle h, double lam_lo, double lam_hi, int32_t nev,

@@ -68,6 +68,14 @@ def load_library():
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is not built (python -m paper_1902_07041_amd.build); "
                            "there is no fallback path")
+    # PyTorch-ROCm ships its own HIP runtime.  Loading torch first makes the
+    # library bind to that same runtime (one HIP runtime per process); loaded
+    # the other way round the process holds two runtimes and the second one
+    # finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(p)
     vp, i32, i64, u32, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
     pd = C.POINTER(C.c_double)
@@ -165,7 +173,7 @@ def pfe_create(device: int = 0, stream=None):
     h = C.c_void_p()
     st = L.pfe_create(device, C.c_void_p(stream) if stream else None, C.byref(h))
     if st != 0:
-        raise PfeError(st, "pfe_create failed")
+        raise PfeError(st, "pfe_create: " + L.pfe_last_error(None).decode())
     return h
 
 
@@ -311,7 +319,7 @@ def pfe_spring_gradient(h, pairs, unit, dblocks, n_atoms: int):
 
 
 def pfe_solve_interval(h, lam_lo, lam_hi, nev, block, degree=0, eps=0.0, r=0.0,
-                       smoothing=PFE_SMOOTH_NONE, tol=1e-10, max_iter=100, precision=PFE_FP64,
+                       smoothing=PFE_SMOOTH_NONE, tol=0.0, max_iter=100, precision=PFE_FP64,
                        seed=11, x0=None, want_vectors=True, vectors_on_device=False,
                        allow_noconv=False):
     """Eigenpairs in [lam_lo, lam_hi].  Returns a dict with evals, evecs

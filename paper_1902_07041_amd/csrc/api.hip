@@ -88,11 +88,11 @@ Err sync(pfe_handle h) {
 
 int64_t round_up(int64_t v, int64_t m) { return ((v + m - 1) / m) * m; }
 
-// Algorithmic HBM bytes of one fused Chebyshev step: matrix values and column
-// indices once, row pointers once, and five multivector streams (T_in once,
-// T_prev read, T_out written, Y read and written).
+// Algorithmic HBM bytes of one Clenshaw step: matrix values and column
+// indices once, row pointers once, and four multivector streams (b_{k+1}
+// gathered once, b_{k+2} and X read, b_k written).
 double step_bytes(int64_t n_atoms, int64_t nnzb, int q, int elem) {
-  return (double)nnzb * (9.0 * elem + 4.0) + 8.0 * (n_atoms + 1) + 5.0 * 3.0 * n_atoms * q * elem;
+  return (double)nnzb * (9.0 * elem + 4.0) + 8.0 * (n_atoms + 1) + 4.0 * 3.0 * n_atoms * q * elem;
 }
 
 struct Timer {
@@ -116,39 +116,57 @@ struct Timer {
 };
 
 // ---------------------------------------------------------------- filter
-// Y = p(A) X by Algorithm 2 with the fused step.  step 1: t1 = a1 (H t0) + b1 t0,
-// steps k >= 2: t_k = a2 (H t_{k-1}) + b2 t_{k-1} - t_{k-2}.  With clobber the
-// caller's X is overwritten (t_2 goes there) and T2 is not needed.
+// Y = p(A) X, A = a1 H + b1 I, by Clenshaw's backward recurrence for a
+// Chebyshev series: b_{d+1} = b_{d+2} = 0, b_k = g_k X + 2 A b_{k+1} - b_{k+2}
+// (k = d..1), Y = g_0 X + A b_1 - b_2.  It evaluates the same polynomial as
+// the forward recurrence of Algorithm 2 with one multivector stream less per
+// step (no running sum to read and write).  b_d = g_d X is never stored: it
+// is folded into the first launch and into the X coefficient of the second.
+// X is read only; the result lands in P, Q is scratch (P, Q, X distinct).
+// d launches for d >= 1.
 template <typename T>
-Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& coef, double a1,
-               double b1, double a2, double b2, T* X, bool clobber, T* Y, T* T1, T* T2, int q,
-               int64_t ld, int64_t* steps) {
+Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double a1, double b1,
+               const T* X, T* P, T* Q, int q, int64_t ld, int64_t* steps) {
   const pfe::Bsr A = h->bsr();
-  auto step = [&](const T* tin, const T* prev, T* out, T* y, double al, double be, double de,
-                  double yk, double go, double gi) -> hipError_t {
+  auto step = [&](const T* tin, const T* prev, T* out, double al, double be, double de,
+                  double ze) -> hipError_t {
     if constexpr (sizeof(T) == 8)
       return pfe::cheb_step_f64(A, (const double*)vals, (const double*)tin, (const double*)prev,
-                                (double*)out, (double*)y, q, ld, al, be, de, yk, go, gi,
-                                h->stream);
+                                (const double*)X, (double*)out, q, ld, al, be, de, ze, h->stream);
     else
       return pfe::cheb_step_f32(A, (const float*)vals, (const float*)tin, (const float*)prev,
-                                (float*)out, (float*)y, q, ld, (float)al, (float)be, (float)de,
-                                (float)yk, (float)go, (float)gi, h->stream);
+                                (const float*)X, (float*)out, q, ld, (float)al, (float)be,
+                                (float)de, (float)ze, h->stream);
   };
-  const int d = (int)coef.size() - 1;
+  const int d = (int)g.size() - 1;
   if (d == 0) {
-    PFE_HIP(step(X, nullptr, T1, Y, 0.0, 0.0, 0.0, 0.0, 0.0, coef[0]));
+    PFE_HIP(step(X, nullptr, P, 0.0, 0.0, 0.0, g[0]));
     if (steps) *steps += 1;
     return pfe::ok();
   }
-  PFE_HIP(step(X, nullptr, T1, Y, a1, b1, 0.0, 0.0, coef[1], coef[0]));
-  T* prev = X;
-  T* cur = T1;
-  for (int k = 2; k <= d; ++k) {
-    T* out = (k == 2) ? (clobber ? X : T2) : prev;
-    PFE_HIP(step(cur, prev, out, Y, a2, b2, -1.0, 1.0, coef[k], 0.0));
-    prev = cur;
-    cur = out;
+  if (d == 1) {
+    PFE_HIP(step(X, nullptr, P, g[1] * a1, g[1] * b1, 0.0, g[0]));
+    if (steps) *steps += 1;
+    return pfe::ok();
+  }
+  // outputs alternate between two buffers; pick the start so the result is P
+  T* buf[2] = {((d - 1) % 2 == 0) ? P : Q, ((d - 1) % 2 == 0) ? Q : P};
+  // b_{d-1} = g_{d-1} X + 2 A (g_d X)
+  PFE_HIP(step(X, nullptr, buf[0], 2.0 * g[d] * a1, 2.0 * g[d] * b1, 0.0, g[d - 1]));
+  if (d == 2) {
+    // Y = g_0 X + A b_1 - b_2, b_2 = g_2 X
+    PFE_HIP(step(buf[0], nullptr, buf[1], a1, b1, 0.0, g[0] - g[2]));
+  } else {
+    // b_{d-2} = g_{d-2} X + 2 A b_{d-1} - g_d X
+    PFE_HIP(step(buf[0], nullptr, buf[1], 2.0 * a1, 2.0 * b1, 0.0, g[d - 2] - g[d]));
+    T* cur = buf[1];   // b_{k+1}
+    T* prv = buf[0];   // b_{k+2}
+    for (int k = d - 3; k >= 1; --k) {
+      PFE_HIP(step(cur, prv, prv, 2.0 * a1, 2.0 * b1, -1.0, g[k]));
+      std::swap(cur, prv);
+    }
+    // Y = g_0 X + A b_1 - b_2, over b_2
+    PFE_HIP(step(cur, prv, prv, a1, b1, -1.0, g[0]));
   }
   if (steps) *steps += d;
   return pfe::ok();
@@ -259,8 +277,8 @@ Err rayleigh_ritz(pfe_handle h, const Small& sm, double* X, double* W, int64_t n
   const pfe::Bsr A = h->bsr();
   {
     Timer tm(h, t_rr);
-    PFE_HIP(pfe::cheb_step_f64(A, h->H.as<double>(), X, nullptr, W, nullptr, q, ld, 1.0, 0.0,
-                               0.0, 0.0, 0.0, 0.0, h->stream));
+    PFE_HIP(pfe::cheb_step_f64(A, h->H.as<double>(), X, nullptr, nullptr, W, q, ld, 1.0, 0.0,
+                               0.0, 0.0, h->stream));
     PFE_HIP(pfe::gram_f64(n, q, q, X, ld, W, ld, sm.S, h->wsRed.p, h->stream));
     PFE_HIP(pfe::sym_eig_f64(q, sm.S, sm.theta, sm.Q, sm.jw, sm.info, h->stream));
     PFE_HIP(pfe::gemm_tall_f64(n, q, q, X, ld, sm.Q, X, ld, h->stream));
@@ -297,34 +315,45 @@ extern "C" {
 
 const char* pfe_version(void) { return "pfeig 0.1 (gfx950)"; }
 
+static thread_local std::string g_create_err;
+
+static pfe_status create_fail(pfe_ctx* h, pfe_status st, const std::string& msg) {
+  g_create_err = msg;
+  if (h) {
+    for (auto& e : h->ev)
+      if (e) (void)hipEventDestroy(e);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+  }
+  return st;
+}
+
 pfe_status pfe_create(int device, void* hip_stream, pfe_handle* out) {
-  if (!out) return PFE_EINVAL;
+  if (!out) return create_fail(nullptr, PFE_EINVAL, "out is NULL");
   *out = nullptr;
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PFE_EHIP;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess)
+    return create_fail(nullptr, PFE_EHIP, std::string("hipGetDeviceCount: ") + hipGetErrorString(e));
+  if (device < 0 || device >= ndev)
+    return create_fail(nullptr, PFE_EINVAL,
+                       "device " + std::to_string(device) + " out of range (" + std::to_string(ndev) + " devices)");
   pfe_ctx* h = new pfe_ctx();
   h->device = device;
-  if (hipSetDevice(device) != hipSuccess) {
-    delete h;
-    return PFE_EHIP;
-  }
+  if ((e = hipSetDevice(device)) != hipSuccess)
+    return create_fail(h, PFE_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
   if (hip_stream) {
     h->stream = static_cast<hipStream_t>(hip_stream);
   } else {
-    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete h;
-      return PFE_EHIP;
-    }
+    if ((e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking)) != hipSuccess)
+      return create_fail(h, PFE_EHIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
     h->own_stream = true;
   }
-  if (hipEventCreate(&h->ev[0]) != hipSuccess || hipEventCreate(&h->ev[1]) != hipSuccess) {
-    delete h;
-    return PFE_EHIP;
-  }
-  if (h->flags.ensure(256) != hipSuccess) {
-    delete h;
-    return PFE_ENOMEM;
-  }
+  if ((e = hipEventCreate(&h->ev[0])) != hipSuccess || (e = hipEventCreate(&h->ev[1])) != hipSuccess)
+    return create_fail(h, PFE_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+  if ((e = h->flags.ensure(256)) != hipSuccess)
+    return create_fail(h, PFE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  g_create_err.clear();
   *out = h;
   return PFE_OK;
 }
@@ -339,7 +368,7 @@ void pfe_destroy(pfe_handle h) {
   delete h;
 }
 
-const char* pfe_last_error(pfe_handle h) { return h ? h->err.c_str() : "null handle"; }
+const char* pfe_last_error(pfe_handle h) { return h ? h->err.c_str() : g_create_err.c_str(); }
 
 int64_t pfe_device_bytes(pfe_handle h) {
   if (!h) return 0;
@@ -356,7 +385,7 @@ void pfe_solve_opts_default(pfe_solve_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->r = std::pow(0.1, 0.25);
   o->smoothing = PFE_SMOOTH_NONE;
-  o->tol = 1e-10;
+  o->tol = 0.0;   // 1e-10 (FP64) or 1e-8 (FP32 filter form)
   o->max_iter = 100;
   o->precision = PFE_FP64;
   o->seed = 11;
@@ -569,7 +598,6 @@ static Err apply_impl(pfe_handle h, const pfe_filter* f, int nvec, const void* X
   const size_t mv = (size_t)n * ld * elem;
   std::vector<double> coef(f->coef, f->coef + f->degree + 1);
   PFE_HIP(h->wsA.ensure(mv));
-  PFE_HIP(h->wsB.ensure(mv));
   if (!dev) {
     PFE_HIP(h->wsC.ensure(mv));
     PFE_HIP(h->wsD.ensure(mv));
@@ -582,14 +610,13 @@ static Err apply_impl(pfe_handle h, const pfe_filter* f, int nvec, const void* X
     Yd = h->wsD.p;
   }
   if (precision == PFE_FP64) {
-    PFE_TRY(run_filter<double>(h, h->H.as<double>(), coef, 1.0 / f->e, -f->c / f->e, 2.0 / f->e,
-                               -2.0 * f->c / f->e, (double*)Xd, false, (double*)Yd,
-                               h->wsA.as<double>(), h->wsB.as<double>(), nvec, ld, nullptr));
+    PFE_TRY(run_filter<double>(h, h->H.as<double>(), coef, 1.0 / f->e, -f->c / f->e,
+                               (const double*)Xd, (double*)Yd, h->wsA.as<double>(), nvec, ld,
+                               nullptr));
   } else {
     PFE_TRY(ensure_h32(h, f->c, f->e));
-    PFE_TRY(run_filter<float>(h, h->H32.as<float>(), coef, 1.0, 0.0, 2.0, 0.0, (float*)Xd, false,
-                              (float*)Yd, h->wsA.as<float>(), h->wsB.as<float>(), nvec, ld,
-                              nullptr));
+    PFE_TRY(run_filter<float>(h, h->H32.as<float>(), coef, 1.0, 0.0, (const float*)Xd,
+                              (float*)Yd, h->wsA.as<float>(), nvec, ld, nullptr));
   }
   if (!dev) PFE_HIP(hipMemcpyAsync(Y, Yd, mv, hipMemcpyDeviceToHost, h->stream));
   PFE_TRY(sync(h));
@@ -613,7 +640,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   pfe_solve_opts o;
   pfe_solve_opts_default(&o);
   if (o_in) o = *o_in;
-  if (o.tol <= 0) o.tol = 1e-10;
+  if (o.tol <= 0) o.tol = (o.precision == PFE_FP32) ? 1e-8 : 1e-10;
   if (o.max_iter <= 0) o.max_iter = 100;
   if (o.r == 0) o.r = std::pow(0.1, 0.25);
   const int q = o.block;
@@ -640,8 +667,9 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   const bool trace = tr_env && tr_env[0] && tr_env[0] != '0';
   const int64_t ld = round_up(q, 8);
   const size_t mv64 = (size_t)n * ld * sizeof(double);
-  // FP64 form: X, Y, W(T).  Mixed form: X64, W64 and a 12-byte/element
-  // region holding X32, T32, Y32 (or, for the refinement sweep, one FP64 Y).
+  // FP64 form: X, W and one FP64 scratch.  Mixed form: X64, W64 and a
+  // 12-byte/element region holding X32, P32, Q32 (or, for the refinement
+  // sweep, one FP64 scratch).
   PFE_HIP(h->wsA.ensure(mv64));
   PFE_HIP(h->wsB.ensure(mv64));
   PFE_HIP(h->wsC.ensure(mixed ? (size_t)n * ld * 12 : mv64));
@@ -681,44 +709,33 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   double prev_max = HUGE_VAL;
   const pfe::Bsr A = h->bsr();
   for (int it = 1; it <= o.max_iter; ++it) {
-    double* Y;
+    // Y = p(H_hat) X into W (X is read only), then Y is orthonormalised in
+    // place and becomes the next basis: the X and W buffers swap roles.
     if (fp64_phase) {
-      // Y = p(H_hat) X in FP64; X is consumed (t_2 lands there)
-      Y = mixed ? (double*)R : W;
-      double* T1 = mixed ? W : (double*)R;
       Timer tm(h, &st.t_filter);
-      PFE_TRY(run_filter<double>(h, h->H.as<double>(), fd.coef, 1.0 / fd.e, -fd.c / fd.e,
-                                 2.0 / fd.e, -2.0 * fd.c / fd.e, X, true, Y, T1, nullptr, q, ld,
-                                 &st.filter_steps));
+      PFE_TRY(run_filter<double>(h, h->H.as<double>(), fd.coef, 1.0 / fd.e, -fd.c / fd.e, X, W,
+                                 (double*)R, q, ld, &st.filter_steps));
       st.filter_bytes += sbytes64 * fd.degree;
       st.fp64_iterations++;
     } else {
       float* X32 = (float*)R;
-      float* T32 = X32 + n * ld;
-      float* Y32 = T32 + n * ld;
+      float* P32 = X32 + n * ld;
+      float* Q32 = P32 + n * ld;
       Timer tm(h, &st.t_filter);
       PFE_HIP(pfe::cast_f64_to_f32(n, q, X, ld, X32, ld, h->stream));
-      PFE_TRY(run_filter<float>(h, h->H32.as<float>(), fd.coef, 1.0, 0.0, 2.0, 0.0, X32, true,
-                                Y32, T32, nullptr, q, ld, &st.filter_steps));
-      PFE_HIP(pfe::cast_f32_to_f64(n, q, Y32, ld, X, ld, h->stream));
+      PFE_TRY(run_filter<float>(h, h->H32.as<float>(), fd.coef, 1.0, 0.0, X32, P32, Q32, q, ld,
+                                &st.filter_steps));
+      PFE_HIP(pfe::cast_f32_to_f64(n, q, P32, ld, W, ld, h->stream));
       st.filter_bytes += sbytes32 * fd.degree;
-      Y = X;
     }
     {
       Timer tm(h, &st.t_orth);
-      PFE_TRY(cholqr2(h, sm, Y, n, q, ld, bound));
+      PFE_TRY(cholqr2(h, sm, W, n, q, ld, bound));
     }
-    if (Y != X) {
-      // make X the orthonormal basis and keep W free for H X
-      if (mixed) {
-        PFE_HIP(pfe::copy_cols_f64(n, q, Y, ld, X, ld, h->stream));
-      } else {
-        std::swap(h->wsA.p, h->wsB.p);
-        std::swap(h->wsA.bytes, h->wsB.bytes);
-        X = h->wsA.as<double>();
-        W = h->wsB.as<double>();
-      }
-    }
+    std::swap(h->wsA.p, h->wsB.p);
+    std::swap(h->wsA.bytes, h->wsB.bytes);
+    X = h->wsA.as<double>();
+    W = h->wsB.as<double>();
     PFE_TRY(rayleigh_ritz(h, sm, X, W, n, q, ld, theta, res, &st.t_rr, &st.t_resid));
     st.iterations = it;
     int cnt = 0;
@@ -739,7 +756,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       converged = ok_all;
       break;   // the single refinement sweep is over
     }
-    if (ok_all && prev_ok && cnt == prev_cnt) {
+    if (ok_all && prev_ok && cnt == prev_cnt && it >= 3) {
       converged = true;
       break;
     }
@@ -822,7 +839,6 @@ static Err count_impl(pfe_handle h, double lam_lo, double lam_hi, int degree, in
   PFE_HIP(h->wsA.ensure(mv));
   PFE_HIP(h->wsB.ensure(mv));
   PFE_HIP(h->wsC.ensure(mv));
-  PFE_HIP(h->wsD.ensure(mv));
   double* Vd = h->wsA.as<double>();
   PFE_HIP(pfe::zero_f64(Vd, n * ld, h->stream));
   if (V) {
@@ -841,13 +857,10 @@ static Err count_impl(pfe_handle h, double lam_lo, double lam_hi, int degree, in
   double* dots = nrm + M;
   PFE_HIP(pfe::col_norms_f64(n, M, Vd, ld, nrm, h->wsRed.p, h->stream));
   PFE_HIP(pfe::col_scale_inv_f64(n, M, Vd, ld, nrm, h->stream));
-  // keep the unit samples in wsD; the filter consumes only copies
-  double* Vk = h->wsD.as<double>();
-  PFE_HIP(pfe::copy_cols_f64(n, (int)ld, Vd, ld, Vk, ld, h->stream));
   double* Y = h->wsB.as<double>();
-  PFE_TRY(run_filter<double>(h, h->H.as<double>(), coef, 1.0 / e, -c / e, 2.0 / e, -2.0 * c / e,
-                             Vd, true, Y, h->wsC.as<double>(), nullptr, M, ld, nullptr));
-  PFE_HIP(pfe::col_dots_f64(n, M, Vk, Y, ld, dots, h->wsRed.p, h->stream));
+  PFE_TRY(run_filter<double>(h, h->H.as<double>(), coef, 1.0 / e, -c / e, Vd, Y,
+                             h->wsC.as<double>(), M, ld, nullptr));
+  PFE_HIP(pfe::col_dots_f64(n, M, Vd, Y, ld, dots, h->wsRed.p, h->stream));
   std::vector<double> hd(M);
   PFE_HIP(hipMemcpyAsync(hd.data(), dots, M * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   PFE_TRY(sync(h));
@@ -906,8 +919,8 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
   PFE_HIP(pfe::zero_f64(G, h->nnzb * 9, h->stream));
   const double a1 = 1.0 / e, b1 = -c / e, a2 = 2.0 / e, b2 = -2.0 * c / e;
   auto fwd = [&](const double* tin, const double* prev, double* out, bool first) -> hipError_t {
-    return pfe::cheb_step_f64(A, Hv, tin, prev, out, nullptr, nvec, ld, first ? a1 : a2,
-                              first ? b1 : b2, first ? 0.0 : -1.0, 0.0, 0.0, 0.0, h->stream);
+    return pfe::cheb_step_f64(A, Hv, tin, prev, nullptr, out, nvec, ld, first ? a1 : a2,
+                              first ? b1 : b2, first ? 0.0 : -1.0, 0.0, h->stream);
   };
   // forward sweep storing (t_{js}, t_{js+1}) for every segment j
   if (d >= 1) {
@@ -947,8 +960,8 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
       PFE_HIP(pfe::copy_cols_f64(n, (int)ld, ck + (2 * j + 1) * nel, ld, seg + nel, ld, h->stream));
     for (int k = k0 + 2; k < k1; ++k)
       PFE_HIP(pfe::cheb_step_f64(A, Hv, seg + (k - 1 - k0) * nel, seg + (k - 2 - k0) * nel,
-                                 seg + (k - k0) * nel, nullptr, nvec, ld, a2, b2, -1.0, 0.0, 0.0,
-                                 0.0, h->stream));
+                                 nullptr, seg + (k - k0) * nel, nvec, ld, a2, b2, -1.0, 0.0,
+                                 h->stream));
     for (int k = k1 - 1; k >= k0; --k) {
       const double* tk = seg + (k - k0) * nel;
       const bool last = (k == 0);

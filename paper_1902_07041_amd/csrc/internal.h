@@ -77,19 +77,17 @@ struct Bsr {
 };
 
 // ------------------------------------------------------------- launchers
-// Fused Chebyshev step (K1):
-//   out = alpha * (H tin) + beta * tin + delta * prev      (prev unused if delta == 0)
-//   y   = y_keep * y + gam_out * out + gam_in * tin          (y unused if y == nullptr;
-//                                                            y not read if y_keep == 0)
-// tin is gathered; out may alias prev; tin must not alias out or y.
-// Rows of all multivectors have stride ld elements; columns [0, q) are processed.
+// Fused Chebyshev step (K1), for every atom row i:
+//   out_i = alpha (H tin)_i + beta tin_i + delta prev_i + zeta add_i
+// (prev not read if delta == 0, add not read if zeta == 0, no neighbour loop
+// if alpha == 0).  tin is gathered and must not alias out; out may alias
+// prev or add.  Rows of all multivectors have stride ld; columns [0, q).
 hipError_t cheb_step_f64(const Bsr& A, const double* vals, const double* tin, const double* prev,
-                         double* out, double* y, int q, int64_t ld, double alpha, double beta,
-                         double delta, double y_keep, double gam_out, double gam_in,
-                         hipStream_t s);
+                         const double* add, double* out, int q, int64_t ld, double alpha,
+                         double beta, double delta, double zeta, hipStream_t s);
 hipError_t cheb_step_f32(const Bsr& A, const float* vals, const float* tin, const float* prev,
-                         float* out, float* y, int q, int64_t ld, float alpha, float beta,
-                         float delta, float y_keep, float gam_out, float gam_in, hipStream_t s);
+                         const float* add, float* out, int q, int64_t ld, float alpha, float beta,
+                         float delta, float zeta, hipStream_t s);
 
 // y = H x for a single vector (q = 1), FP64.
 hipError_t spmv_f64(const Bsr& A, const double* vals, const double* x, double* y, hipStream_t s);

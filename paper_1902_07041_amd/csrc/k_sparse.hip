@@ -10,6 +10,8 @@
 // and the nine block values are wave-uniform and go through scalar loads.
 // Work-groups are remapped so that every XCD walks a contiguous range of
 // atom rows (neighbouring rows share T_in rows in that XCD's L2).
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace pfe {
@@ -24,15 +26,12 @@ struct VT<T, 1> {
   typedef T type;
 };
 
-#ifndef PFE_CHEB_XCD_REMAP
-#define PFE_CHEB_XCD_REMAP 1   // each XCD walks a contiguous range of rows
-#endif
 #ifndef PFE_CHEB_NT_OUT
 #define PFE_CHEB_NT_OUT 1       // T_out written with the nontemporal hint
 #endif
 constexpr int kWavesPerBlock = 4;
 #ifndef PFE_CHEB_UNROLL
-#define PFE_CHEB_UNROLL 8
+#define PFE_CHEB_UNROLL 4
 #endif
 constexpr int kUnroll = PFE_CHEB_UNROLL;
 
@@ -47,16 +46,31 @@ __device__ __forceinline__ void st_nt(V v, V* p) {
   __builtin_nontemporal_store(v, p);
 }
 
-// Epilogue shared by both variants: out = alpha acc + beta tin + delta prev,
-// y = y_keep y + gam_out out + gam_in tin.
+// One fused step computes, for every atom row i and every column,
+//   out_i = alpha (H tin)_i + beta tin_i + delta prev_i + zeta add_i,
+// which covers every recurrence the library runs: Clenshaw's backward
+// recurrence for p(H_hat) X (b_k = g_k X + 2 H_hat b_{k+1} - b_{k+2}),
+// the forward three-term recurrence of Algorithm 2 (adjoint checkpoints),
+// and W = H X.  Four multivector streams at most: tin gathered, prev and add
+// read, out written (out may alias prev or add).
+//
+// Row-to-work-group mapping: work-groups are dispatched round-robin over the
+// 8 XCDs (work-group b runs on XCD b % 8).  Rows are cut into chunks of
+// `chunk` work-groups; chunk c is placed on XCD c % 8, so consecutive rows
+// of a chunk share one XCD's L2 while all XCDs advance through the same
+// region of the matrix together (shared Infinity Cache window).
+__device__ __forceinline__ int map_block(int b, int chunk) {
+  const int xcd = b & 7, s = b >> 3;
+  return ((s / chunk) * 8 + xcd) * chunk + (s % chunk);
+}
+
 template <typename T, int VW, int NP>
-__device__ __forceinline__ void cheb_epilogue(typename VT<T, VW>::type (&acc)[3][NP],
+__device__ __forceinline__ void step_epilogue(typename VT<T, VW>::type (&acc)[3][NP],
                                               const bool (&act)[NP], int row, int lane, int col0,
-                                              const T* __restrict__ tin, const T* prev, T* out,
-                                              T* y, int64_t ld, T alpha, T beta, T delta,
-                                              T y_keep, T gam_out, T gam_in) {
+                                              const T* __restrict__ tin, const T* prev,
+                                              const T* add, T* out, int64_t ld, T alpha, T beta,
+                                              T delta, T zeta) {
   using vt = typename VT<T, VW>::type;
-  const bool need_tin = (beta != T(0)) || (y != nullptr && gam_in != T(0));
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     if (!act[p]) continue;
@@ -65,21 +79,13 @@ __device__ __forceinline__ void cheb_epilogue(typename VT<T, VW>::type (&acc)[3]
     for (int a = 0; a < 3; ++a) {
       const int64_t off = (int64_t)(3 * row + a) * ld + col0 + c;
       vt o = alpha * acc[a][p];
-      vt ti = vt(0);
-      if (need_tin) {
-        ti = *reinterpret_cast<const vt*>(tin + off);
-        o += beta * ti;
-      }
+      if (beta != T(0)) o += beta * *reinterpret_cast<const vt*>(tin + off);
       if (delta != T(0)) o += delta * ld_nt(reinterpret_cast<const vt*>(prev + off));
+      if (zeta != T(0)) o += zeta * ld_nt(reinterpret_cast<const vt*>(add + off));
       if (PFE_CHEB_NT_OUT)
         st_nt(o, reinterpret_cast<vt*>(out + off));
       else
         *reinterpret_cast<vt*>(out + off) = o;
-      if (y != nullptr) {
-        vt yv = gam_out * o + gam_in * ti;
-        if (y_keep != T(0)) yv += y_keep * ld_nt(reinterpret_cast<const vt*>(y + off));
-        st_nt(yv, reinterpret_cast<vt*>(y + off));
-      }
     }
   }
 }
@@ -88,11 +94,10 @@ __device__ __forceinline__ void cheb_epilogue(typename VT<T, VW>::type (&acc)[3]
 template <typename T, int VW, int NP, int U>
 __global__ __launch_bounds__(256) void k_cheb_step(
     int n_atoms, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-    const T* __restrict__ vals, const T* __restrict__ tin, const T* prev, T* out, T* y, int q,
-    int64_t ld, T alpha, T beta, T delta, T y_keep, T gam_out, T gam_in, int per_xcd) {
+    const T* __restrict__ vals, const T* __restrict__ tin, const T* prev, const T* add, T* out,
+    int q, int64_t ld, T alpha, T beta, T delta, T zeta, int chunk) {
   using vt = typename VT<T, VW>::type;
-  const int b = blockIdx.x;
-  const int lb = PFE_CHEB_XCD_REMAP ? (b & 7) * per_xcd + (b >> 3) : b;
+  const int lb = map_block(blockIdx.x, chunk);
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int row = uniform(lb * kWavesPerBlock + wave);
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(256) void k_cheb_step(
     act[p] = col0 + (lane + 64 * p) * VW < q;
   }
   const int64_t b0 = row_ptr[row];
-  const int64_t b1 = row_ptr[row + 1];
+  const int64_t b1 = (alpha != T(0)) ? row_ptr[row + 1] : b0;
   // col_idx and vals are padded by kBsrPad entries on the device, so the U
   // index and value loads of a group are unconditional; lanes of neighbours
   // past the row end read zeros instead of T_in.
@@ -150,27 +155,25 @@ __global__ __launch_bounds__(256) void k_cheb_step(
       }
     }
   }
-  cheb_epilogue<T, VW, NP>(acc, act, row, lane, col0, tin, prev, out, y, ld, alpha, beta, delta,
-                           y_keep, gam_out, gam_in);
+  step_epilogue<T, VW, NP>(acc, act, row, lane, col0, tin, prev, add, out, ld, alpha, beta, delta,
+                           zeta);
 }
 
 // Variant L: the work-group first stages the column indices and block values
 // of its four rows (one contiguous range of blocks) in LDS with coalesced
 // loads; each wave then takes its row's neighbours U at a time, reading the
-// indices and values as LDS broadcasts, so the only long-latency step per
-// group is the batch of T_in gathers.
+// indices and values as LDS broadcasts.
 constexpr int kStageBlocks = 128;
 
 template <typename T, int VW, int NP, int U>
 __global__ __launch_bounds__(256) void k_cheb_step_lds(
     int n_atoms, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-    const T* __restrict__ vals, const T* __restrict__ tin, const T* prev, T* out, T* y, int q,
-    int64_t ld, T alpha, T beta, T delta, T y_keep, T gam_out, T gam_in, int per_xcd) {
+    const T* __restrict__ vals, const T* __restrict__ tin, const T* prev, const T* add, T* out,
+    int q, int64_t ld, T alpha, T beta, T delta, T zeta, int chunk) {
   using vt = typename VT<T, VW>::type;
   __shared__ T s_val[kStageBlocks * 9];
   __shared__ int s_col[kStageBlocks + U];
-  const int b = blockIdx.x;
-  const int lb = PFE_CHEB_XCD_REMAP ? (b & 7) * per_xcd + (b >> 3) : b;
+  const int lb = map_block(blockIdx.x, chunk);
   const int r0 = lb * kWavesPerBlock;
   if (r0 >= n_atoms) return;                       // uniform over the work-group
   const int wave = uniform(threadIdx.x >> 6);
@@ -180,7 +183,8 @@ __global__ __launch_bounds__(256) void k_cheb_step_lds(
   const bool row_ok = row < n_atoms;
   const int r_end = min(r0 + kWavesPerBlock, n_atoms);
   const int col0 = blockIdx.y * (64 * NP * VW);
-  const int64_t wb0 = row_ptr[r0], wb1 = row_ptr[r_end];
+  const int64_t wb0 = row_ptr[r0];
+  const int64_t wb1 = (alpha != T(0)) ? row_ptr[r_end] : wb0;
   const int64_t b0 = row_ok ? row_ptr[row] : wb1;
   const int64_t b1 = row_ok ? row_ptr[row + 1] : wb1;
 
@@ -240,30 +244,44 @@ __global__ __launch_bounds__(256) void k_cheb_step_lds(
     }
   }
   if (!row_ok) return;
-  cheb_epilogue<T, VW, NP>(acc, act, row, lane, col0, tin, prev, out, y, ld, alpha, beta, delta,
-                           y_keep, gam_out, gam_in);
+  step_epilogue<T, VW, NP>(acc, act, row, lane, col0, tin, prev, add, out, ld, alpha, beta, delta,
+                           zeta);
 }
 
 #ifndef PFE_CHEB_VARIANT
-#define PFE_CHEB_VARIANT 1   // 0: scalar, 1: LDS-staged
+#define PFE_CHEB_VARIANT 0   // 0: scalar, 1: LDS-staged
+#endif
+#ifndef PFE_CHEB_CHUNK
+#define PFE_CHEB_CHUNK 64    // work-groups per XCD chunk (measured best on MI355X); 0: one range per XCD
 #endif
 
+int chunk_override() {
+  static int v = [] {
+    const char* e = std::getenv("PFEIG_CHEB_CHUNK");
+    return e ? std::atoi(e) : -1;
+  }();
+  return v;
+}
+
 template <typename T, int VW, int NP>
-hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, T* out, T* y,
-                       int q, int64_t ld, T alpha, T beta, T delta, T y_keep, T gam_out, T gam_in,
+hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, const T* add,
+                       T* out, int q, int64_t ld, T alpha, T beta, T delta, T zeta,
                        hipStream_t s) {
   const int64_t nblk = (A.n_atoms + kWavesPerBlock - 1) / kWavesPerBlock;
-  const int per_xcd = (int)((nblk + 7) / 8);
+  const int64_t per_xcd = (nblk + 7) / 8;
+  int chunk = chunk_override() > 0 ? chunk_override() : PFE_CHEB_CHUNK;
+  if (chunk <= 0 || chunk > per_xcd) chunk = (int)per_xcd;
+  const int64_t grid_x = ((nblk + 8LL * chunk - 1) / (8LL * chunk)) * 8LL * chunk;
   const int cols_per_group = 64 * NP * VW;
-  dim3 grid((unsigned)(per_xcd * 8), (unsigned)((q + cols_per_group - 1) / cols_per_group));
+  dim3 grid((unsigned)grid_x, (unsigned)((q + cols_per_group - 1) / cols_per_group));
   if (PFE_CHEB_VARIANT == 1)
     hipLaunchKernelGGL((k_cheb_step_lds<T, VW, NP, kUnroll>), grid, dim3(256), 0, s,
-                       (int)A.n_atoms, A.row_ptr, A.col_idx, vals, tin, prev, out, y, q, ld,
-                       alpha, beta, delta, y_keep, gam_out, gam_in, per_xcd);
+                       (int)A.n_atoms, A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, ld,
+                       alpha, beta, delta, zeta, chunk);
   else
     hipLaunchKernelGGL((k_cheb_step<T, VW, NP, kUnroll>), grid, dim3(256), 0, s, (int)A.n_atoms,
-                       A.row_ptr, A.col_idx, vals, tin, prev, out, y, q, ld, alpha, beta, delta,
-                       y_keep, gam_out, gam_in, per_xcd);
+                       A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, ld, alpha, beta,
+                       delta, zeta, chunk);
   return hipGetLastError();
 }
 
@@ -275,9 +293,9 @@ bool aligned(const void* p, int bytes) {
 // Chooses the vector width (largest that divides q and ld with aligned
 // pointers) and the number of column passes per lane.
 template <typename T, int MAXVW>
-hipError_t dispatch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, T* out, T* y,
-                         int q, int64_t ld, T alpha, T beta, T delta, T y_keep, T gam_out,
-                         T gam_in, hipStream_t s) {
+hipError_t dispatch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, const T* add,
+                         T* out, int q, int64_t ld, T alpha, T beta, T delta, T zeta,
+                         hipStream_t s) {
   if (A.n_atoms == 0 || q == 0) return hipSuccess;
   // smallest vector width that covers q with one 64-lane pass, if the
   // layout allows it; otherwise the widest that does
@@ -286,7 +304,7 @@ hipError_t dispatch_cheb(const Bsr& A, const T* vals, const T* tin, const T* pre
   auto fits = [&](int v) {
     const int bytes = v * (int)sizeof(T);
     return q % v == 0 && ld % v == 0 && aligned<T>(tin, bytes) && aligned<T>(prev, bytes) &&
-           aligned<T>(out, bytes) && aligned<T>(y, bytes);
+           aligned<T>(out, bytes) && aligned<T>(add, bytes);
   };
   int vw = want;
   while (vw > 1 && !fits(vw)) vw /= 2;
@@ -294,8 +312,8 @@ hipError_t dispatch_cheb(const Bsr& A, const T* vals, const T* tin, const T* pre
   const int np = chunks <= 64 ? 1 : (chunks <= 128 ? 2 : 4);
 #define PFE_CHEB_CASE(VW_, NP_)                                                               \
   if (vw == VW_ && np == NP_)                                                                 \
-    return launch_cheb<T, VW_, NP_>(A, vals, tin, prev, out, y, q, ld, alpha, beta, delta,    \
-                                    y_keep, gam_out, gam_in, s);
+    return launch_cheb<T, VW_, NP_>(A, vals, tin, prev, add, out, q, ld, alpha, beta, delta,  \
+                                    zeta, s);
   PFE_CHEB_CASE(1, 1)
   PFE_CHEB_CASE(1, 2)
   PFE_CHEB_CASE(1, 4)
@@ -423,18 +441,16 @@ inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 }  // namespace
 
 hipError_t cheb_step_f64(const Bsr& A, const double* vals, const double* tin, const double* prev,
-                         double* out, double* y, int q, int64_t ld, double alpha, double beta,
-                         double delta, double y_keep, double gam_out, double gam_in,
-                         hipStream_t s) {
-  return dispatch_cheb<double, 4>(A, vals, tin, prev, out, y, q, ld, alpha, beta, delta, y_keep,
-                                  gam_out, gam_in, s);
+                         const double* add, double* out, int q, int64_t ld, double alpha,
+                         double beta, double delta, double zeta, hipStream_t s) {
+  return dispatch_cheb<double, 4>(A, vals, tin, prev, add, out, q, ld, alpha, beta, delta, zeta,
+                                  s);
 }
 
 hipError_t cheb_step_f32(const Bsr& A, const float* vals, const float* tin, const float* prev,
-                         float* out, float* y, int q, int64_t ld, float alpha, float beta,
-                         float delta, float y_keep, float gam_out, float gam_in, hipStream_t s) {
-  return dispatch_cheb<float, 8>(A, vals, tin, prev, out, y, q, ld, alpha, beta, delta, y_keep,
-                                 gam_out, gam_in, s);
+                         const float* add, float* out, int q, int64_t ld, float alpha, float beta,
+                         float delta, float zeta, hipStream_t s) {
+  return dispatch_cheb<float, 8>(A, vals, tin, prev, add, out, q, ld, alpha, beta, delta, zeta, s);
 }
 
 hipError_t spmv_f64(const Bsr& A, const double* vals, const double* x, double* y, hipStream_t s) {

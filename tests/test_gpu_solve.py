@@ -65,7 +65,7 @@ def test_solve_fp64_matches_oracle_si(case):
 def test_solve_fp32_form(case):
     banner("solve fp32-filter form N=1000")
     X0 = gaussian_block(case.n, 32, 11)
-    out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-9,
+    out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-8,
                                precision=P.PFE_FP32, x0=X0)
     assert out["status"] == "PFE_OK", out["stats"]
     check_pairs(case, out, 1e-8, 1e-8)

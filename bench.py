@@ -233,7 +233,7 @@ def main() -> int:
                       "sum_m_dlam_dm_over_sum_lam": float(np.dot(g.masses, dm)) / lam_sum},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(q, d),
-                     "kernel": "k_cheb_step<double,2,1> (fused BSR3 Clenshaw step)",
+                     "kernel": "k_cheb_tile<double,2,1,2,2> (fused BSR3 Clenshaw step, 2-row tiles)",
                      "avg_launch_us": 1e6 * avg_launch,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }

@@ -28,6 +28,9 @@ struct pfe_ctx {
   int64_t n_atoms = 0, nnzb = 0;
   bool has_h = false, has_masses = false;
   DevBuf row_ptr, col_idx, H, transpose, masses, H32;
+  int tile_rows = 0;
+  int64_t n_tiles = 0;
+  DevBuf tile_ptr, tile_vptr, tile_cm, tile_perm, Ht, H32row;
   double h32_c = NAN, h32_e = NAN;
   // bounds
   bool has_bounds = false;
@@ -47,7 +50,16 @@ struct pfe_ctx {
     a.nnzb = nnzb;
     a.row_ptr = row_ptr.as<int64_t>();
     a.col_idx = col_idx.as<int32_t>();
+    a.tile_rows = tile_rows;
+    a.n_tiles = n_tiles;
+    a.tile_ptr = tile_ptr.as<int64_t>();
+    a.tile_vptr = tile_vptr.as<int64_t>();
+    a.tile_cm = tile_cm.as<int2>();
     return a;
+  }
+  // Block values as the fused step reads them (tile order when tiles are on).
+  const double* step_vals64() const {
+    return tile_rows >= 2 ? Ht.as<double>() : H.as<double>();
   }
   int64_t n() const { return 3 * n_atoms; }
 };
@@ -87,6 +99,11 @@ Err sync(pfe_handle h) {
 }
 
 int64_t round_up(int64_t v, int64_t m) { return ((v + m - 1) / m) * m; }
+
+#ifndef PFE_TILE_ROWS
+#define PFE_TILE_ROWS 2
+#endif
+constexpr int kDefaultTileRows = PFE_TILE_ROWS;
 
 // Algorithmic HBM bytes of one Clenshaw step: matrix values and column
 // indices once, row pointers once, and four multivector streams (b_{k+1}
@@ -174,10 +191,22 @@ Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double
 
 Err ensure_h32(pfe_handle h, double c, double e) {
   if (h->H32.p && h->h32_c == c && h->h32_e == e) return pfe::ok();
-  PFE_HIP(h->H32.ensure((size_t)(h->nnzb + pfe::kBsrPad) * 9 * sizeof(float)));
-  PFE_HIP(pfe::zero_f32(h->H32.as<float>(), (h->nnzb + pfe::kBsrPad) * 9, h->stream));
-  PFE_HIP(pfe::shift_scale_to_f32(h->bsr(), h->H.as<double>(), c, e, h->H32.as<float>(),
-                                  h->stream));
+  const int64_t nel = (h->nnzb + pfe::kBsrPad) * 9;
+  PFE_HIP(h->H32.ensure((size_t)nel * sizeof(float)));
+  PFE_HIP(pfe::zero_f32(h->H32.as<float>(), nel, h->stream));
+  if (h->tile_rows >= 2) {
+    // formed in row order (diagonal blocks known there), then put in tile order
+    PFE_HIP(h->H32row.ensure((size_t)nel * sizeof(float)));
+    PFE_HIP(pfe::shift_scale_to_f32(h->bsr(), h->H.as<double>(), c, e, h->H32row.as<float>(),
+                                    h->stream));
+    PFE_HIP(pfe::permute_blocks_f32(h->nnzb, h->tile_perm.as<int64_t>(), h->H32row.as<float>(),
+                                    h->H32.as<float>(), h->stream));
+    PFE_HIP(hipStreamSynchronize(h->stream));
+    h->H32row.release();
+  } else {
+    PFE_HIP(pfe::shift_scale_to_f32(h->bsr(), h->H.as<double>(), c, e, h->H32.as<float>(),
+                                    h->stream));
+  }
   h->h32_c = c;
   h->h32_e = e;
   return pfe::ok();
@@ -277,7 +306,7 @@ Err rayleigh_ritz(pfe_handle h, const Small& sm, double* X, double* W, int64_t n
   const pfe::Bsr A = h->bsr();
   {
     Timer tm(h, t_rr);
-    PFE_HIP(pfe::cheb_step_f64(A, h->H.as<double>(), X, nullptr, nullptr, W, q, ld, 1.0, 0.0,
+    PFE_HIP(pfe::cheb_step_f64(A, h->step_vals64(), X, nullptr, nullptr, W, q, ld, 1.0, 0.0,
                                0.0, 0.0, h->stream));
     PFE_HIP(pfe::gram_f64(n, q, q, X, ld, W, ld, sm.S, h->wsRed.p, h->stream));
     PFE_HIP(pfe::sym_eig_f64(q, sm.S, sm.theta, sm.Q, sm.jw, sm.info, h->stream));
@@ -372,7 +401,8 @@ const char* pfe_last_error(pfe_handle h) { return h ? h->err.c_str() : g_create_
 
 int64_t pfe_device_bytes(pfe_handle h) {
   if (!h) return 0;
-  const DevBuf* bufs[] = {&h->row_ptr, &h->col_idx, &h->H,    &h->transpose, &h->masses,
+  const DevBuf* bufs[] = {&h->tile_ptr, &h->tile_vptr, &h->tile_cm, &h->tile_perm, &h->Ht,
+                          &h->row_ptr, &h->col_idx, &h->H,    &h->transpose, &h->masses,
                           &h->H32,     &h->flags,   &h->wsA,  &h->wsB,       &h->wsC,
                           &h->wsD,     &h->wsSmall, &h->wsRed, &h->wsOut,    &h->wsCk};
   int64_t s = 0;
@@ -449,6 +479,43 @@ static Err set_hessian_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const i
   if (weight) {
     PFE_HIP(pfe::mass_weight(A, h->H.as<double>(), h->masses.as<double>(), h->H.as<double>(),
                              h->stream));
+  }
+  // row tiles for the fused filter step (rows per tile: PFEIG_TILE_ROWS, else
+  // the default measured best on MI355X)
+  int R = kDefaultTileRows;
+  if (const char* e = std::getenv("PFEIG_TILE_ROWS")) R = std::atoi(e);
+  h->tile_rows = 0;
+  h->n_tiles = 0;
+  if (R >= 2 && R <= 4) {
+    std::vector<int32_t> ci((size_t)nnzb);
+    if (dev) {
+      PFE_HIP(hipMemcpy(ci.data(), col_idx, nnzb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    } else {
+      std::memcpy(ci.data(), col_idx, nnzb * sizeof(int32_t));
+    }
+    std::vector<int64_t> tp, tv, perm;
+    std::vector<int32_t> tcm;
+    pfe::build_row_tiles(n_atoms, rp.data(), ci.data(), R, tp, tv, tcm, perm);
+    PFE_HIP(h->tile_ptr.ensure(tp.size() * sizeof(int64_t)));
+    PFE_HIP(h->tile_vptr.ensure(tv.size() * sizeof(int64_t)));
+    PFE_HIP(h->tile_cm.ensure(tcm.size() * sizeof(int32_t)));
+    PFE_HIP(h->tile_perm.ensure(perm.size() * sizeof(int64_t)));
+    PFE_HIP(h->Ht.ensure((size_t)(nnzb + pfe::kBsrPad) * 9 * sizeof(double)));
+    PFE_HIP(hipMemcpy(h->tile_ptr.p, tp.data(), tp.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    PFE_HIP(hipMemcpy(h->tile_vptr.p, tv.data(), tv.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    PFE_HIP(hipMemcpy(h->tile_cm.p, tcm.data(), tcm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    PFE_HIP(hipMemcpy(h->tile_perm.p, perm.data(), perm.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    PFE_HIP(pfe::zero_f64(h->Ht.as<double>(), (nnzb + pfe::kBsrPad) * 9, h->stream));
+    PFE_HIP(pfe::permute_blocks_f64(nnzb, h->tile_perm.as<int64_t>(), h->H.as<double>(),
+                                    h->Ht.as<double>(), h->stream));
+    h->tile_rows = R;
+    h->n_tiles = (int64_t)tp.size() - 1;
+  } else {
+    h->tile_ptr.release();
+    h->tile_vptr.release();
+    h->tile_cm.release();
+    h->tile_perm.release();
+    h->Ht.release();
   }
   PFE_TRY(sync(h));
   h->has_h = true;
@@ -610,7 +677,7 @@ static Err apply_impl(pfe_handle h, const pfe_filter* f, int nvec, const void* X
     Yd = h->wsD.p;
   }
   if (precision == PFE_FP64) {
-    PFE_TRY(run_filter<double>(h, h->H.as<double>(), coef, 1.0 / f->e, -f->c / f->e,
+    PFE_TRY(run_filter<double>(h, h->step_vals64(), coef, 1.0 / f->e, -f->c / f->e,
                                (const double*)Xd, (double*)Yd, h->wsA.as<double>(), nvec, ld,
                                nullptr));
   } else {
@@ -713,7 +780,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     // place and becomes the next basis: the X and W buffers swap roles.
     if (fp64_phase) {
       Timer tm(h, &st.t_filter);
-      PFE_TRY(run_filter<double>(h, h->H.as<double>(), fd.coef, 1.0 / fd.e, -fd.c / fd.e, X, W,
+      PFE_TRY(run_filter<double>(h, h->step_vals64(), fd.coef, 1.0 / fd.e, -fd.c / fd.e, X, W,
                                  (double*)R, q, ld, &st.filter_steps));
       st.filter_bytes += sbytes64 * fd.degree;
       st.fp64_iterations++;
@@ -858,7 +925,7 @@ static Err count_impl(pfe_handle h, double lam_lo, double lam_hi, int degree, in
   PFE_HIP(pfe::col_norms_f64(n, M, Vd, ld, nrm, h->wsRed.p, h->stream));
   PFE_HIP(pfe::col_scale_inv_f64(n, M, Vd, ld, nrm, h->stream));
   double* Y = h->wsB.as<double>();
-  PFE_TRY(run_filter<double>(h, h->H.as<double>(), coef, 1.0 / e, -c / e, Vd, Y,
+  PFE_TRY(run_filter<double>(h, h->step_vals64(), coef, 1.0 / e, -c / e, Vd, Y,
                              h->wsC.as<double>(), M, ld, nullptr));
   PFE_HIP(pfe::col_dots_f64(n, M, Vd, Y, ld, dots, h->wsRed.p, h->stream));
   std::vector<double> hd(M);
@@ -914,12 +981,13 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
   double* ck = h->wsCk.as<double>();
   double* G = h->wsD.as<double>();
   const pfe::Bsr A = h->bsr();
-  const double* Hv = h->H.as<double>();
+  const double* Hv = h->H.as<double>();       // row order (reverse step)
+  const double* Hs = h->step_vals64();       // as the fused step reads it
   const int32_t* tr = h->transpose.as<int32_t>();
   PFE_HIP(pfe::zero_f64(G, h->nnzb * 9, h->stream));
   const double a1 = 1.0 / e, b1 = -c / e, a2 = 2.0 / e, b2 = -2.0 * c / e;
   auto fwd = [&](const double* tin, const double* prev, double* out, bool first) -> hipError_t {
-    return pfe::cheb_step_f64(A, Hv, tin, prev, nullptr, out, nvec, ld, first ? a1 : a2,
+    return pfe::cheb_step_f64(A, Hs, tin, prev, nullptr, out, nvec, ld, first ? a1 : a2,
                               first ? b1 : b2, first ? 0.0 : -1.0, 0.0, h->stream);
   };
   // forward sweep storing (t_{js}, t_{js+1}) for every segment j
@@ -959,7 +1027,7 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
     if (k1 - k0 >= 2)
       PFE_HIP(pfe::copy_cols_f64(n, (int)ld, ck + (2 * j + 1) * nel, ld, seg + nel, ld, h->stream));
     for (int k = k0 + 2; k < k1; ++k)
-      PFE_HIP(pfe::cheb_step_f64(A, Hv, seg + (k - 1 - k0) * nel, seg + (k - 2 - k0) * nel,
+      PFE_HIP(pfe::cheb_step_f64(A, Hs, seg + (k - 1 - k0) * nel, seg + (k - 2 - k0) * nel,
                                  nullptr, seg + (k - k0) * nel, nvec, ld, a2, b2, -1.0, 0.0,
                                  h->stream));
     for (int k = k1 - 1; k >= k0; --k) {

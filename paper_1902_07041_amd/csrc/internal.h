@@ -74,7 +74,30 @@ struct Bsr {
   int64_t nnzb = 0;
   const int64_t* row_ptr = nullptr;   // [n_atoms+1]
   const int32_t* col_idx = nullptr;   // [nnzb]
+  // Row tiles (optional, tile_rows >= 2): R = tile_rows consecutive block rows
+  // form a tile.  Tile t owns union columns [tile_ptr[t], tile_ptr[t+1]) of
+  // tile_cm, each a (column, row mask) pair (bit r set when row t*R + r
+  // stores a block in that column), sorted by column.  With tiles active the
+  // fused step reads its block values in tile order: the blocks of tile t
+  // start at tile_vptr[t] and follow (union column, row) order.  tile_cm
+  // carries kBsrPad padded entries.
+  int tile_rows = 0;
+  int64_t n_tiles = 0;
+  const int64_t* tile_ptr = nullptr;
+  const int64_t* tile_vptr = nullptr;
+  const int2* tile_cm = nullptr;
 };
+
+// Host construction of the row tiles of a block-CSR pattern (see Bsr);
+// perm[p] is the row-order index of the block at tile-order position p.
+void build_row_tiles(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col_idx, int R,
+                     std::vector<int64_t>& tile_ptr, std::vector<int64_t>& tile_vptr,
+                     std::vector<int32_t>& tile_cm, std::vector<int64_t>& perm);
+// dst[p] = src[perm[p]] for 3x3 blocks (FP64 and FP32).
+hipError_t permute_blocks_f64(int64_t nnzb, const int64_t* perm, const double* src, double* dst,
+                              hipStream_t s);
+hipError_t permute_blocks_f32(int64_t nnzb, const int64_t* perm, const float* src, float* dst,
+                              hipStream_t s);
 
 // ------------------------------------------------------------- launchers
 // Fused Chebyshev step (K1), for every atom row i:

@@ -10,7 +10,9 @@
 // and the nine block values are wave-uniform and go through scalar loads.
 // Work-groups are remapped so that every XCD walks a contiguous range of
 // atom rows (neighbouring rows share T_in rows in that XCD's L2).
+#include <algorithm>
 #include <cstdlib>
+#include <vector>
 
 #include "internal.h"
 
@@ -34,6 +36,10 @@ constexpr int kWavesPerBlock = 4;
 #define PFE_CHEB_UNROLL 4
 #endif
 constexpr int kUnroll = PFE_CHEB_UNROLL;
+#ifndef PFE_TILE_UNROLL
+#define PFE_TILE_UNROLL 2
+#endif
+constexpr int kTileUnroll = PFE_TILE_UNROLL;   // union columns gathered per batch (tiles)
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -248,6 +254,105 @@ __global__ __launch_bounds__(256) void k_cheb_step_lds(
                            zeta);
 }
 
+// Variant T (row tiles): one wave per tile of R consecutive block rows.  Each
+// union column j of the tile is gathered once (three rows of T_in) and
+// applied to every row of the tile that stores block (row, j), so a T_in row
+// shared by neighbouring output rows costs one set of vector loads instead of
+// up to R.  Block values are read in tile order from a running offset, so
+// their scalar loads depend only on the (column, mask) record.
+template <typename T, int VW, int NP, int U, int R>
+__global__ __launch_bounds__(256) void k_cheb_tile(
+    int n_atoms, int n_tiles, const int64_t* __restrict__ tile_ptr,
+    const int64_t* __restrict__ tile_vptr, const int2* __restrict__ tile_cm,
+    const T* __restrict__ vals, const T* __restrict__ tin, const T* prev, const T* add, T* out,
+    int q, int64_t ld, T alpha, T beta, T delta, T zeta, int chunk) {
+  using vt = typename VT<T, VW>::type;
+  const int lb = map_block(blockIdx.x, chunk);
+  const int wave = uniform(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tile = uniform(lb * kWavesPerBlock + wave);
+  if (tile >= n_tiles) return;
+  const int col0 = blockIdx.y * (64 * NP * VW);
+  vt acc[R][3][NP];
+  bool act[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      acc[r][0][p] = vt(0);
+      acc[r][1][p] = vt(0);
+      acc[r][2][p] = vt(0);
+    }
+    act[p] = col0 + (lane + 64 * p) * VW < q;
+  }
+  const int64_t u0 = tile_ptr[tile];
+  const int64_t u1 = (alpha != T(0)) ? tile_ptr[tile + 1] : u0;
+  int64_t voff = tile_vptr[tile];
+  const int own = tile * R;
+  for (int64_t k = u0; k < u1; k += U) {
+    vt x[U][3][NP];
+    int2 cm[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cm[u] = tile_cm[k + u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool valid = (u == 0) || (k + u < u1);
+      const T* src = tin + (int64_t)(3 * (valid ? cm[u].x : own)) * ld + col0;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int c = (lane + 64 * p) * VW;
+        if (act[p] && valid) {
+          x[u][0][p] = *reinterpret_cast<const vt*>(src + c);
+          x[u][1][p] = *reinterpret_cast<const vt*>(src + ld + c);
+          x[u][2][p] = *reinterpret_cast<const vt*>(src + 2 * ld + c);
+        } else {
+          x[u][0][p] = vt(0);
+          x[u][1][p] = vt(0);
+          x[u][2][p] = vt(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (u == 0 || k + u < u1) {
+        const int m = cm[u].y;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if ((m >> r) & 1) {
+            const T* hv = vals + voff * 9;
+            ++voff;
+            T h[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) h[t] = hv[t];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+              acc[r][0][p] += h[0] * x[u][0][p] + h[1] * x[u][1][p] + h[2] * x[u][2][p];
+              acc[r][1][p] += h[3] * x[u][0][p] + h[4] * x[u][1][p] + h[5] * x[u][2][p];
+              acc[r][2][p] += h[6] * x[u][0][p] + h[7] * x[u][1][p] + h[8] * x[u][2][p];
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int row = own + r;
+    if (row < n_atoms)
+      step_epilogue<T, VW, NP>(acc[r], act, row, lane, col0, tin, prev, add, out, ld, alpha,
+                               beta, delta, zeta);
+  }
+}
+
+template <typename T>
+__global__ void k_permute_blocks(int64_t nnzb, const int64_t* __restrict__ perm,
+                                 const T* __restrict__ src, T* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnzb * 9) return;
+  const int64_t p = i / 9, t = i % 9;
+  dst[i] = src[perm[p] * 9 + t];
+}
+
 #ifndef PFE_CHEB_VARIANT
 #define PFE_CHEB_VARIANT 0   // 0: scalar, 1: LDS-staged
 #endif
@@ -267,21 +372,37 @@ template <typename T, int VW, int NP>
 hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, const T* add,
                        T* out, int q, int64_t ld, T alpha, T beta, T delta, T zeta,
                        hipStream_t s) {
-  const int64_t nblk = (A.n_atoms + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int R = (A.tile_rows >= 2 && A.tile_ptr) ? A.tile_rows : 1;   // vals in tile order
+  const int64_t units = (R >= 2) ? A.n_tiles : A.n_atoms;   // one wave per unit
+  const int64_t nblk = (units + kWavesPerBlock - 1) / kWavesPerBlock;
   const int64_t per_xcd = (nblk + 7) / 8;
   int chunk = chunk_override() > 0 ? chunk_override() : PFE_CHEB_CHUNK;
+  if (R >= 2) chunk = std::max(1, chunk / R);   // keep rows per chunk comparable
   if (chunk <= 0 || chunk > per_xcd) chunk = (int)per_xcd;
   const int64_t grid_x = ((nblk + 8LL * chunk - 1) / (8LL * chunk)) * 8LL * chunk;
   const int cols_per_group = 64 * NP * VW;
   dim3 grid((unsigned)grid_x, (unsigned)((q + cols_per_group - 1) / cols_per_group));
-  if (PFE_CHEB_VARIANT == 1)
+  if (R == 2) {
+    hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 2>), grid, dim3(256), 0, s,
+                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm, vals,
+                       tin, prev, add, out, q, ld, alpha, beta, delta, zeta, chunk);
+  } else if (R == 3) {
+    hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 3>), grid, dim3(256), 0, s,
+                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm, vals,
+                       tin, prev, add, out, q, ld, alpha, beta, delta, zeta, chunk);
+  } else if (R == 4) {
+    hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 4>), grid, dim3(256), 0, s,
+                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm, vals,
+                       tin, prev, add, out, q, ld, alpha, beta, delta, zeta, chunk);
+  } else if (PFE_CHEB_VARIANT == 1) {
     hipLaunchKernelGGL((k_cheb_step_lds<T, VW, NP, kUnroll>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, ld,
                        alpha, beta, delta, zeta, chunk);
-  else
+  } else {
     hipLaunchKernelGGL((k_cheb_step<T, VW, NP, kUnroll>), grid, dim3(256), 0, s, (int)A.n_atoms,
                        A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, ld, alpha, beta,
                        delta, zeta, chunk);
+  }
   return hipGetLastError();
 }
 
@@ -488,6 +609,60 @@ hipError_t validate_masses(int64_t n_atoms, const double* masses, int* err_flags
   if (n_atoms == 0) return hipSuccess;
   hipLaunchKernelGGL(k_validate_masses, dim3(nb(n_atoms, 256)), dim3(256), 0, s, (int)n_atoms,
                      masses, err_flags);
+  return hipGetLastError();
+}
+
+void build_row_tiles(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col_idx, int R,
+                     std::vector<int64_t>& tile_ptr, std::vector<int64_t>& tile_vptr,
+                     std::vector<int32_t>& tile_cm, std::vector<int64_t>& perm) {
+  const int64_t n_tiles = (n_atoms + R - 1) / R;
+  tile_ptr.assign(n_tiles + 1, 0);
+  tile_vptr.assign(n_tiles, 0);
+  tile_cm.clear();
+  perm.clear();
+  perm.reserve(row_ptr[n_atoms]);
+  std::vector<std::pair<int32_t, int64_t>> ent;   // (column, r << 40 | block)
+  for (int64_t t = 0; t < n_tiles; ++t) {
+    ent.clear();
+    const int64_t r0 = t * R, r1 = std::min<int64_t>(r0 + R, n_atoms);
+    for (int64_t row = r0; row < r1; ++row)
+      for (int64_t b = row_ptr[row]; b < row_ptr[row + 1]; ++b)
+        ent.emplace_back(col_idx[b], ((row - r0) << 40) | b);
+    std::sort(ent.begin(), ent.end());   // by column, then row
+    tile_vptr[t] = (int64_t)perm.size();
+    int64_t nu = 0;
+    for (size_t e = 0; e < ent.size();) {
+      const int32_t c = ent[e].first;
+      int32_t mask = 0;
+      for (; e < ent.size() && ent[e].first == c; ++e) {
+        mask |= 1 << (int)(ent[e].second >> 40);
+        perm.push_back(ent[e].second & ((1LL << 40) - 1));
+      }
+      tile_cm.push_back(c);
+      tile_cm.push_back(mask);
+      ++nu;
+    }
+    tile_ptr[t + 1] = tile_ptr[t] + nu;
+  }
+  for (int64_t p = 0; p < kBsrPad; ++p) {
+    tile_cm.push_back(0);
+    tile_cm.push_back(0);
+  }
+}
+
+hipError_t permute_blocks_f64(int64_t nnzb, const int64_t* perm, const double* src, double* dst,
+                              hipStream_t s) {
+  if (nnzb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute_blocks<double>, dim3((unsigned)((nnzb * 9 + 255) / 256)),
+                     dim3(256), 0, s, nnzb, perm, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t permute_blocks_f32(int64_t nnzb, const int64_t* perm, const float* src, float* dst,
+                              hipStream_t s) {
+  if (nnzb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute_blocks<float>, dim3((unsigned)((nnzb * 9 + 255) / 256)),
+                     dim3(256), 0, s, nnzb, perm, src, dst);
   return hipGetLastError();
 }
 

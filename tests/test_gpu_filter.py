@@ -114,3 +114,25 @@ def test_set_hessian_validation():
         P.pfe_set_hessian(h, g.row_ptr, g.col_idx, g.blocks, g.masses)
     finally:
         P.pfe_destroy(h)
+
+
+@pytest.mark.parametrize("tile_rows", ["1", "2", "4"])
+@pytest.mark.parametrize("q", [1, 96, 160])
+def test_filter_row_tile_variants(case, tile_rows, q, monkeypatch):
+    """Every tiling of the fused step (rows per tile read at Hessian import)."""
+    banner(f"apply_filter tile_rows={tile_rows} q={q}")
+    monkeypatch.setenv("PFEIG_TILE_ROWS", tile_rows)
+    g = case.g
+    h = P.pfe_create(0)
+    try:
+        # N = 1000 is not a multiple of 4 * 64 rows: ragged last tile and chunk
+        P.pfe_set_hessian(h, g.row_ptr, g.col_idx, g.blocks, g.masses)
+        P.pfe_set_bounds(h, 0.0, case.ub)
+        f = design(case, 25)
+        for prec in (np.float64, np.float32):
+            X = gaussian_block(case.n, q, 300 + q).astype(prec)
+            Y = P.pfe_apply_filter(h, f, X)
+            ref = chebyshev.apply_filter(case.H, f.c, f.e, f.coef, X.astype(np.float64))
+            assert rel_err(Y, ref) < (1e-12 if prec == np.float64 else 5e-5)
+    finally:
+        P.pfe_destroy(h)

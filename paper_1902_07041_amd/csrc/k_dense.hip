@@ -338,6 +338,114 @@ __global__ __launch_bounds__(1024) void k_jacobi(int q, const double* __restrict
   if (tid == 0) info[0] = converged ? sweep : -sweep;
 }
 
+// LDS-resident variant for q <= kJacobiLdsMax: A and V^T live in LDS with
+// row stride q+1 (column sweeps hit distinct banks); same ordering, skip
+// rule and stopping rule as k_jacobi.
+constexpr int kJacobiLdsMax = 96;
+
+__global__ __launch_bounds__(1024) void k_jacobi_lds(int q, const double* __restrict__ S,
+                                                     double* __restrict__ evals,
+                                                     double* __restrict__ Q, int* info) {
+  __shared__ double A[kJacobiLdsMax * (kJacobiLdsMax + 1)];
+  __shared__ double VT[kJacobiLdsMax * (kJacobiLdsMax + 1)];
+  __shared__ double cs[kJacobiLdsMax / 2 + 1], sn[kJacobiLdsMax / 2 + 1];
+  __shared__ int pp[kJacobiLdsMax / 2 + 1], qq[kJacobiLdsMax / 2 + 1];
+  __shared__ int rotated;
+  __shared__ double red[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int ldq = q + 1;
+  const int m = q + (q & 1);
+  const int half = m / 2;
+  double loc = 0.0;
+  for (int idx = tid; idx < q * q; idx += nt) {
+    const int i = idx / q, j = idx % q;
+    const double a = 0.5 * (S[i * q + j] + S[j * q + i]);
+    A[i * ldq + j] = a;
+    VT[i * ldq + j] = (i == j) ? 1.0 : 0.0;
+    loc += a * a;
+  }
+  red[tid] = loc;
+  __syncthreads();
+  for (int s = nt / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double floor_abs = 1e-18 * sqrt(red[0]) + 1e-300;
+  const double eps = 2.220446049250313e-16;
+  int sweep = 0;
+  bool converged = (q < 2);
+  for (; sweep < 60 && !converged; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int step = 0; step < m - 1; ++step) {
+      if (tid < half) {
+        int p, r;
+        rr_pair(m, step, tid, &p, &r);
+        double c = 1.0, s = 0.0;
+        if (p < q && r < q) {
+          const double apq = A[p * ldq + r];
+          const double app = A[p * ldq + p], arr = A[r * ldq + r];
+          if (fabs(apq) > floor_abs && fabs(apq) > eps * sqrt(fabs(app * arr))) {
+            const double theta = (arr - app) / (2.0 * apq);
+            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+            rotated = 1;
+          }
+        }
+        cs[tid] = c;
+        sn[tid] = s;
+        pp[tid] = p;
+        qq[tid] = r;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < half * q; idx += nt) {   // rows p, r of A and of V^T
+        const int k = idx / q, j = idx % q;
+        const double s = sn[k];
+        if (s == 0.0) continue;
+        const double c = cs[k];
+        const int p = pp[k], r = qq[k];
+        const double a = A[p * ldq + j], b = A[r * ldq + j];
+        A[p * ldq + j] = c * a - s * b;
+        A[r * ldq + j] = s * a + c * b;
+        const double va = VT[p * ldq + j], vb = VT[r * ldq + j];
+        VT[p * ldq + j] = c * va - s * vb;
+        VT[r * ldq + j] = s * va + c * vb;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < half * q; idx += nt) {   // columns p, r of A
+        const int k = idx / q, i = idx % q;
+        const double s = sn[k];
+        if (s == 0.0) continue;
+        const double c = cs[k];
+        const int p = pp[k], r = qq[k];
+        const double a = A[i * ldq + p], b = A[i * ldq + r];
+        A[i * ldq + p] = c * a - s * b;
+        A[i * ldq + r] = s * a + c * b;
+      }
+      __syncthreads();
+      if (tid < half && sn[tid] != 0.0) {
+        A[pp[tid] * ldq + qq[tid]] = 0.0;
+        A[qq[tid] * ldq + pp[tid]] = 0.0;
+      }
+      __syncthreads();
+    }
+    converged = (rotated == 0);
+    __syncthreads();
+  }
+  for (int i = tid; i < q; i += nt) {
+    const double di = A[i * ldq + i];
+    int rank = 0;
+    for (int j = 0; j < q; ++j) {
+      const double dj = A[j * ldq + j];
+      if (dj < di || (dj == di && j < i)) ++rank;
+    }
+    evals[rank] = di;
+    for (int r = 0; r < q; ++r) Q[r * q + rank] = VT[i * ldq + r];
+  }
+  if (tid == 0) info[0] = converged ? sweep : -sweep;
+}
+
 // ------------------------------------------------------- column reductions
 constexpr int kColRows = 512;   // rows per partial block
 
@@ -650,6 +758,10 @@ size_t jacobi_work_bytes(int q) { return (size_t)2 * q * q * sizeof(double); }
 hipError_t sym_eig_f64(int q, const double* S, double* evals, double* Q, void* work, int* info,
                        hipStream_t s) {
   if (q > 1024) return hipErrorInvalidValue;
+  if (q <= kJacobiLdsMax) {
+    hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(1024), 0, s, q, S, evals, Q, info);
+    return hipGetLastError();
+  }
   double* A = static_cast<double*>(work);
   double* V = A + (int64_t)q * q;
   hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, q, S, A, V, evals, Q, info);

@@ -88,6 +88,23 @@ pfe_status pfe_set_hessian(pfe_handle h, int64_t n_atoms, int64_t nnzb,
                            const int64_t* row_ptr, const int32_t* col_idx,
                            const double* blocks, const double* masses, uint32_t flags);
 
+/* Import a harmonic spring network (the pair-potential Hessian of Sec. 1,
+ * eq. intro.1, with one spring constant per pair): spring p joins atoms
+ * pairs[p] = (i, j) with 0 <= i < j < n_atoms, listed in strictly increasing
+ * (i, j) order, along the unit vector unit[p][3] and with constant k[p].  On
+ * the device K_ij = K_ji = -k_p u_p u_p^T, K_ii = -sum_{j != i} K_ij on the
+ * given BSR pattern, which must hold exactly the diagonal blocks and both
+ * orientations of every spring (nnzb = n_atoms + 2 n_springs; EINVAL
+ * otherwise, or if an off-diagonal block has no spring); then everything
+ * pfe_set_hessian does with these K and masses (mass weighting, validation).
+ * hblocks_out (nullable, [nnzb][3][3], same side as the inputs) receives
+ * H = M^{-1/2} K M^{-1/2} in the pattern's order.  pairs, unit and k are only
+ * read during the call; the spring gradient call takes them again. */
+pfe_status pfe_set_springs(pfe_handle h, int64_t n_atoms, int64_t nnzb, const int64_t* row_ptr,
+                           const int32_t* col_idx, int64_t n_springs, const int64_t* pairs,
+                           const double* unit, const double* k, const double* masses,
+                           double* hblocks_out, uint32_t flags);
+
 /* ----------------------------------------------------------------- bounds
  * `steps` Lanczos steps with full re-orthogonalisation on H (Algorithm 3,
  * step 3) from start vector v0 (length n; NULL: a seeded Gaussian vector from

@@ -6,7 +6,8 @@ entry module and the CPU-baseline leg of the benchmark use it.  It shares no
 code with the HIP library: it is written directly from the paper
 (Accaputo, Derlet, Arbenz, "Solving large-scale interior eigenvalue problems
 to investigate the vibrational properties of the boson peak regime in
-amorphous materials", 2019) with numpy/scipy/LAPACK as the only primitives.
+amorphous materials", 2019) with numpy/scipy/LAPACK as the only primitives,
+plus one plain C loop (cbsr.c) for the block-sparse product at large sizes.
 
 Modules
 -------
@@ -17,6 +18,8 @@ filters     piecewise-quadratic target p (Sec. 2.6, eq. fct_f), its Chebyshev
             Dirac-delta filter (Sec. 2.5, eq. cheby-delta.1)
 chebyshev   Algorithm 2, y = p_d(H) x by the three-term recurrence
 lanczos     a few Lanczos steps for the extremal-eigenvalue bounds (Alg. 3)
+cbsr        H @ X by the textbook block-CSR loop in C (OpenMP over rows), a
+            drop-in for the scipy matrix when n is in the hundreds of thousands
 dense       the plain definition: all eigenpairs of H in a closed window
 subspace    filtered subspace iteration with Rayleigh-Ritz (Alg. 4, adapted)
 count       stochastic trace estimate of the eigenvalue count (eq.

@@ -25,6 +25,30 @@ def weight_blocks(row_ptr, col_idx, blocks, masses) -> np.ndarray:
     return blocks * w[:, None, None]
 
 
+def spring_blocks(row_ptr, col_idx, pairs, unit, k) -> np.ndarray:
+    """K on a given block pattern for harmonic springs (eq. intro.1 with the
+    pair energy k_p (u_p . (x_j - x_i))^2 / 2): the bond block between i and j
+    is -k_p u_p u_p^T, the diagonal block the negative sum of its row's bond
+    blocks.  Plain loops over the stored blocks; a block without a spring
+    raises."""
+    lookup = {(int(i), int(j)): p for p, (i, j) in enumerate(np.asarray(pairs))}
+    rows = block_rows(row_ptr)
+    K = np.zeros((len(col_idx), 3, 3))
+    diag = {}
+    for b in range(len(col_idx)):
+        i, j = int(rows[b]), int(col_idx[b])
+        if i == j:
+            diag[i] = b
+            continue
+        p = lookup[(min(i, j), max(i, j))]
+        K[b] = -k[p] * np.outer(unit[p], unit[p])
+    for b in range(len(col_idx)):
+        i, j = int(rows[b]), int(col_idx[b])
+        if i != j:
+            K[diag[i]] -= K[b]
+    return K
+
+
 def to_bsr(row_ptr, col_idx, hblocks) -> sp.bsr_matrix:
     n_atoms = row_ptr.shape[0] - 1
     return sp.bsr_matrix((np.ascontiguousarray(hblocks), np.asarray(col_idx, dtype=np.int64),

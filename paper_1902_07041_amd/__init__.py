@@ -12,6 +12,7 @@ from ._capi import (PFE_FP32, PFE_FP64, PFE_SMOOTH_JACKSON, PFE_SMOOTH_LANCZOS, 
                     pfe_apply_filter_adjoint, pfe_create, pfe_design_filter, pfe_destroy,
                     pfe_device_bytes, pfe_eigvec_block_gradient, pfe_estimate_bounds,
                     pfe_estimate_count, pfe_last_error, pfe_set_bounds, pfe_set_hessian,
+                    pfe_set_springs,
                     pfe_solve_interval, pfe_spring_gradient, pfe_version)
 
 __all__ = [
@@ -19,6 +20,6 @@ __all__ = [
     "Filter", "PfeError", "STATUS", "lib_path", "load_library", "pfe_apply_filter",
     "pfe_apply_filter_adjoint", "pfe_create", "pfe_design_filter", "pfe_destroy",
     "pfe_device_bytes", "pfe_eigvec_block_gradient", "pfe_estimate_bounds", "pfe_estimate_count",
-    "pfe_last_error", "pfe_set_bounds", "pfe_set_hessian", "pfe_solve_interval",
+    "pfe_last_error", "pfe_set_bounds", "pfe_set_hessian", "pfe_set_springs", "pfe_solve_interval",
     "pfe_spring_gradient", "pfe_version",
 ]

@@ -88,6 +88,7 @@ def load_library():
     L.pfe_device_bytes.argtypes = [vp]
     L.pfe_device_bytes.restype = i64
     L.pfe_set_hessian.argtypes = [vp, i64, i64, vp, vp, vp, vp, u32]
+    L.pfe_set_springs.argtypes = [vp, i64, i64, vp, vp, i64, vp, vp, vp, vp, vp, u32]
     L.pfe_estimate_bounds.argtypes = [vp, i32, vp, u64, u32, pd, pd, pd]
     L.pfe_set_bounds.argtypes = [vp, dbl, dbl]
     L.pfe_design_filter.argtypes = [dbl, dbl, dbl, dbl, C.POINTER(CFilterOpts), pd, i32,
@@ -102,7 +103,7 @@ def load_library():
     L.pfe_solve_interval.argtypes = [vp, dbl, dbl, i32, C.POINTER(CSolveOpts), C.POINTER(i32), vp,
                                      vp, vp, C.POINTER(CSolveStats)]
     L.pfe_estimate_count.argtypes = [vp, dbl, dbl, i32, i32, i32, vp, u64, u32, pd]
-    for name in ("pfe_create", "pfe_set_hessian", "pfe_estimate_bounds", "pfe_set_bounds",
+    for name in ("pfe_create", "pfe_set_hessian", "pfe_set_springs", "pfe_estimate_bounds", "pfe_set_bounds",
                  "pfe_design_filter", "pfe_apply_filter", "pfe_apply_filter_adjoint",
                  "pfe_eigvec_block_gradient", "pfe_spring_gradient", "pfe_solve_interval",
                  "pfe_estimate_count"):
@@ -201,6 +202,28 @@ def pfe_set_hessian(h, row_ptr, col_idx, blocks, masses=None, blocks_are_h=False
     flags = (PFE_DEVICE_PTRS if dev else 0) | (PFE_BLOCKS_ARE_H if blocks_are_h else 0)
     _check(h, L.pfe_set_hessian(h, n_atoms, nnzb, p_rp, p_ci, p_bl, p_m, flags))
     _N[h.value] = 3 * n_atoms
+
+
+def pfe_set_springs(h, row_ptr, col_idx, pairs, unit, k, masses, want_blocks=False):
+    """Spring-network Hessian assembled on the device; returns H's blocks
+    ([nnzb,3,3], on the inputs' side) when want_blocks."""
+    L = load_library()
+    n_atoms = int(row_ptr.shape[0]) - 1
+    nnzb = int(col_idx.shape[0])
+    P = int(pairs.shape[0])
+    out = _empty_like_side(k, (nnzb, 3, 3), np.float64) if want_blocks else None
+    p_rp, d1 = _arr(row_ptr, np.int64, "row_ptr")
+    p_ci, d2 = _arr(col_idx, np.int32, "col_idx")
+    p_pr, d3 = _arr(pairs, np.int64, "pairs")
+    p_un, d4 = _arr(unit, np.float64, "unit")
+    p_k, d5 = _arr(k, np.float64, "k")
+    p_m, d6 = _arr(masses, np.float64, "masses")
+    p_o, d7 = _arr(out, np.float64, "hblocks")
+    dev = _same_side(d1, d2, d3, d4, d5, d6, d7)
+    _check(h, L.pfe_set_springs(h, n_atoms, nnzb, p_rp, p_ci, P, p_pr, p_un, p_k, p_m, p_o,
+                                PFE_DEVICE_PTRS if dev else 0))
+    _N[h.value] = 3 * n_atoms
+    return out
 
 
 def pfe_estimate_bounds(h, steps: int = 30, v0=None, seed: int = 7):

@@ -422,9 +422,11 @@ void pfe_solve_opts_default(pfe_solve_opts* o) {
 }
 
 // ----------------------------------------------------------- set_hessian
+// blocks_dev: `blocks` is device memory whatever PFE_DEVICE_PTRS says (the
+// spring assembly hands over its own device buffer).
 static Err set_hessian_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const int64_t* row_ptr,
                             const int32_t* col_idx, const double* blocks, const double* masses,
-                            uint32_t flags) {
+                            uint32_t flags, bool blocks_dev = false) {
   PFE_TRY(select_device(h));
   if (n_atoms <= 0 || nnzb < n_atoms || !row_ptr || !col_idx || !blocks)
     return pfe::fail(PFE_EINVAL, "need n_atoms > 0, nnzb >= n_atoms and non-null arrays");
@@ -458,7 +460,7 @@ static Err set_hessian_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const i
   PFE_HIP(hipMemcpyAsync(h->row_ptr.p, rp.data(), rp.size() * sizeof(int64_t),
                          hipMemcpyHostToDevice, h->stream));
   PFE_TRY(upload(h, h->col_idx.as<int32_t>(), col_idx, nnzb, dev));
-  PFE_TRY(upload(h, h->H.as<double>(), blocks, nnzb * 9, dev));
+  PFE_TRY(upload(h, h->H.as<double>(), blocks, nnzb * 9, dev || blocks_dev));
   int* eflag = h->flags.as<int>();
   PFE_HIP(hipMemsetAsync(eflag, 0, sizeof(int), h->stream));
   const pfe::Bsr A = h->bsr();
@@ -528,6 +530,85 @@ pfe_status pfe_set_hessian(pfe_handle h, int64_t n_atoms, int64_t nnzb, const in
                            uint32_t flags) {
   if (!h) return PFE_EINVAL;
   return finish(h, set_hessian_impl(h, n_atoms, nnzb, row_ptr, col_idx, blocks, masses, flags));
+}
+
+// Spring network: K assembled on the device, then the same import as above.
+static Err set_springs_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const int64_t* row_ptr,
+                            const int32_t* col_idx, int64_t P, const int64_t* pairs,
+                            const double* unit, const double* k, const double* masses,
+                            double* hblocks_out, uint32_t flags) {
+  PFE_TRY(select_device(h));
+  if (n_atoms <= 0 || P < 0 || !row_ptr || !col_idx || !masses || (P > 0 && (!pairs || !unit || !k)))
+    return pfe::fail(PFE_EINVAL, "need n_atoms > 0, n_springs >= 0 and non-null arrays");
+  if (nnzb != n_atoms + 2 * P)
+    return pfe::fail(PFE_EINVAL, "the pattern must hold the diagonal and both orientations of every spring "
+                                 "(nnzb = n_atoms + 2 n_springs)");
+  if (n_atoms > (int64_t)INT32_MAX / 3 || nnzb >= (int64_t)INT32_MAX)
+    return pfe::fail(PFE_EINVAL, "sizes exceed the 32-bit index range of the kernels");
+  const bool dev = (flags & PFE_DEVICE_PTRS) != 0;
+  std::vector<int64_t> rp(n_atoms + 1);
+  if (dev) {
+    PFE_HIP(hipMemcpy(rp.data(), row_ptr, rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(rp.data(), row_ptr, rp.size() * sizeof(int64_t));
+  }
+  if (rp[0] != 0 || rp[n_atoms] != nnzb)
+    return pfe::fail(PFE_EINVAL, "row_ptr must start at 0 and end at nnzb");
+  for (int64_t i = 0; i < n_atoms; ++i)
+    if (rp[i + 1] < rp[i]) return pfe::fail(PFE_EINVAL, "row_ptr must be non-decreasing");
+  // staging: K, and device copies of host inputs
+  const size_t bK = (size_t)nnzb * 9 * sizeof(double);
+  const size_t need = bK + (dev ? 0 : (size_t)(n_atoms + 1) * 8 + (size_t)nnzb * 4 + (size_t)P * 48) + 256;
+  pfe::DevBuf stage;
+  PFE_HIP(stage.ensure(need));
+  char* base = stage.as<char>();
+  double* K = (double*)base;
+  const int64_t* rpd = row_ptr;
+  const int32_t* cid = col_idx;
+  const int64_t* prd = pairs;
+  const double* und = unit;
+  const double* kd = k;
+  if (!dev) {
+    int64_t* a = (int64_t*)(base + bK);
+    int64_t* b = a + (n_atoms + 1);
+    double* c = (double*)(b + 2 * P);
+    double* d = c + 3 * P;
+    int32_t* e = (int32_t*)(d + P);
+    PFE_TRY(upload(h, a, row_ptr, n_atoms + 1, false));
+    PFE_TRY(upload(h, b, pairs, 2 * P, false));
+    PFE_TRY(upload(h, c, unit, 3 * P, false));
+    PFE_TRY(upload(h, d, k, P, false));
+    PFE_TRY(upload(h, e, col_idx, nnzb, false));
+    rpd = a;
+    prd = b;
+    und = c;
+    kd = d;
+    cid = e;
+  }
+  int* eflag = h->flags.as<int>() + 8;
+  PFE_HIP(hipMemsetAsync(eflag, 0, sizeof(int), h->stream));
+  PFE_HIP(pfe::assemble_springs(n_atoms, rpd, cid, P, prd, und, kd, K, eflag, h->stream));
+  int ef = 0;
+  PFE_HIP(hipMemcpyAsync(&ef, eflag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  PFE_TRY(sync(h));
+  if (ef & 32) return pfe::fail(PFE_EINVAL, "spring pairs must satisfy 0 <= i < j < n_atoms in strictly increasing order");
+  if (ef & 64) return pfe::fail(PFE_EINVAL, "an off-diagonal block of the pattern has no spring");
+  if (ef & 1) return pfe::fail(PFE_EINVAL, "diagonal block missing");
+  PFE_TRY(set_hessian_impl(h, n_atoms, nnzb, row_ptr, col_idx, K, masses, flags & ~PFE_BLOCKS_ARE_H, true));
+  if (hblocks_out) {
+    PFE_TRY(download(h, hblocks_out, h->H.as<double>(), nnzb * 9, dev));
+    PFE_TRY(sync(h));
+  }
+  return pfe::ok();
+}
+
+pfe_status pfe_set_springs(pfe_handle h, int64_t n_atoms, int64_t nnzb, const int64_t* row_ptr,
+                           const int32_t* col_idx, int64_t n_springs, const int64_t* pairs,
+                           const double* unit, const double* k, const double* masses,
+                           double* hblocks_out, uint32_t flags) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, set_springs_impl(h, n_atoms, nnzb, row_ptr, col_idx, n_springs, pairs, unit, k,
+                                    masses, hblocks_out, flags));
 }
 
 // ----------------------------------------------------------------- bounds

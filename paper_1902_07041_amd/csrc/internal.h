@@ -209,6 +209,13 @@ hipError_t adjoint_step_f64(const Bsr& A, const int32_t* transpose, const double
 // G[b] (+)= sum_c colw_c a[3i+p][c] t[3j+q][c] for stored b = (i, j); q <= 256.
 hipError_t sddmm_f64(const Bsr& A, int q, const double* a, const double* t, int64_t ld,
                      const double* colw, double* G, bool accumulate, hipStream_t s);
+// K blocks of a spring network on a BSR pattern (K_ij = -k u u^T, K_ii = -sum
+// of the row's off-diagonal blocks).  err bit 5: pairs out of range or not in
+// strictly increasing (i < j) order; bit 6: a block without a spring; bit 0: no
+// diagonal block in a row.
+hipError_t assemble_springs(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col_idx,
+                            int64_t P, const int64_t* pairs, const double* unit, const double* k,
+                            double* K, int* err, hipStream_t s);
 // dk[p] and dm[i] from block gradients G; err bit 0: a spring's block missing.
 hipError_t spring_chain(const Bsr& A, const int32_t* transpose, const double* H,
                         const double* masses, const double* G, int64_t P, const int64_t* pairs,

@@ -215,6 +215,77 @@ __global__ void k_spring_dm(int n_atoms, const int64_t* __restrict__ row_ptr,
   dm[i] = -0.5 * s / m[i];
 }
 
+// Spring list checks: 0 <= i < j < n_atoms and strictly increasing (i, j)
+// order, so the assembly can binary-search it.  err bit 5.
+__global__ void k_check_pairs(int64_t P, int n_atoms, const int64_t* __restrict__ pairs, int* err) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
+  bool bad = i < 0 || j >= n_atoms || i >= j;
+  if (p + 1 < P) {
+    const int64_t i2 = pairs[2 * p + 2], j2 = pairs[2 * p + 3];
+    bad = bad || !(i < i2 || (i == i2 && j < j2));
+  }
+  if (bad) atomicOr(err, 32);
+}
+
+__device__ int64_t find_pair(const int64_t* pairs, int64_t P, int64_t i, int64_t j) {
+  int64_t lo = 0, hi = P - 1;
+  while (lo <= hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int64_t pi = pairs[2 * mid], pj = pairs[2 * mid + 1];
+    if (pi == i && pj == j) return mid;
+    if (pi < i || (pi == i && pj < j))
+      lo = mid + 1;
+    else
+      hi = mid - 1;
+  }
+  return -1;
+}
+
+// K of a harmonic spring network on a given BSR pattern, one thread per block
+// row: K_ij = -k_p u_p u_p^T for the spring p joining i and j, and
+// K_ii = -sum_{j != i} K_ij.  err bit 6: an off-diagonal block has no spring;
+// bit 0: the row has no diagonal block.
+__global__ void k_assemble_springs(int n_atoms, const int64_t* __restrict__ row_ptr,
+                                   const int32_t* __restrict__ col_idx, int64_t P,
+                                   const int64_t* __restrict__ pairs,
+                                   const double* __restrict__ unit, const double* __restrict__ kv,
+                                   double* __restrict__ K, int* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_atoms) return;
+  double dg[9];
+  for (int e = 0; e < 9; ++e) dg[e] = 0.0;
+  int64_t bd = -1;
+  for (int64_t b = row_ptr[i]; b < row_ptr[i + 1]; ++b) {
+    const int j = col_idx[b];
+    if (j == i) {
+      bd = b;
+      continue;
+    }
+    const int64_t p = find_pair(pairs, P, i < j ? i : j, i < j ? j : i);
+    if (p < 0) {
+      atomicOr(err, 64);
+      for (int e = 0; e < 9; ++e) K[b * 9 + e] = 0.0;
+      continue;
+    }
+    const double u[3] = {unit[3 * p], unit[3 * p + 1], unit[3 * p + 2]};
+    const double kp = kv[p];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) {
+        // u_a u_c first: the product commutes exactly, so K_ji = K_ij^T bit for bit
+        const double v = -kp * (u[a] * u[c]);
+        K[b * 9 + 3 * a + c] = v;
+        dg[3 * a + c] -= v;
+      }
+  }
+  if (bd < 0) {
+    atomicOr(err, 1);
+    return;
+  }
+  for (int e = 0; e < 9; ++e) K[bd * 9 + e] = dg[e];
+}
+
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -270,6 +341,17 @@ hipError_t spring_chain(const Bsr& A, const int32_t* transpose, const double* H,
   if (A.n_atoms > 0)
     hipLaunchKernelGGL(k_spring_dm, dim3(nb(A.n_atoms, 256)), dim3(256), 0, s, (int)A.n_atoms,
                        A.row_ptr, transpose, H, masses, G, dm);
+  return hipGetLastError();
+}
+
+hipError_t assemble_springs(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col_idx,
+                            int64_t P, const int64_t* pairs, const double* unit, const double* k,
+                            double* K, int* err, hipStream_t s) {
+  if (P > 0)
+    hipLaunchKernelGGL(k_check_pairs, dim3(nb(P, 256)), dim3(256), 0, s, P, (int)n_atoms, pairs, err);
+  if (n_atoms > 0)
+    hipLaunchKernelGGL(k_assemble_springs, dim3(nb(n_atoms, 256)), dim3(256), 0, s, (int)n_atoms,
+                       row_ptr, col_idx, P, pairs, unit, k, K, err);
   return hipGetLastError();
 }
 

@@ -4,14 +4,19 @@
 One step is one pass of the whole hot path over the resident synthetic input
 (a spring-network glass of N = 100,000 atoms, n = 300,000, 3x3 FP64 blocks):
 
-  a1  import + mass-weight the Hessian           pfe_set_hessian (device inputs)
-  a2  30-step Lanczos bounds                      pfe_estimate_bounds
-  a3-a7  FP64 solve: filter design, Chebyshev filter (Clenshaw), CholQR2,
+  a1  assemble K from the springs, mass-weight, validate   SpringSystem.assemble
+      (pfe_set_springs, device inputs; differentiable in k and m)
+  a2  30-step Lanczos bounds                               pfe_estimate_bounds
+  a3  filter design (degree 400)                           pfe_design_filter
+  a4  one filter application Y = p(H_hat) X at q = 96       pfe_apply_filter
+      (its launches are the roofline measurement)
+  a3-a7  FP64 solve: Chebyshev filter (Clenshaw) with locking, CholQR2,
       Rayleigh-Ritz, residuals -> all eigenpairs in the window
   a8  the same solve with the FP32 filter + one FP64 refinement sweep
-  a9  reverse mode: adjoint of p(H)X (block 64, degree 150, sqrt(d)
-      checkpoints), Hellmann-Feynman gradient of the 32 lowest eigenvalues,
-      chain rule to all spring constants and masses
+  a9  reverse mode through torch.autograd: L = <dY, p(H_hat) X> (block 64,
+      degree 150, sqrt(d) checkpoints) back to X, every spring constant and
+      mass; Hellmann-Feynman gradient of the 32 lowest eigenvalues found,
+      chain rule to springs and masses
 
 Prints one JSON line (see --help).  `value` is the wall time of one step in
 seconds (lower is better); the FP64 and FP32-form solve times, the filter
@@ -106,13 +111,41 @@ def cpu_baseline(g, H_bounds, stats64, W):
     }
 
 
+def copy_calibration() -> int:
+    """Device-to-device copy of 2 GiB (reads 2 GiB, writes 2 GiB per copy):
+    the scale for FETCH_SIZE / WRITE_SIZE counters and the achievable copy
+    bandwidth."""
+    import torch
+    nbytes = 2 * 2**30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    print(json.dumps({"copy_bytes": nbytes, "seconds_per_copy": t,
+                      "copy_GBps_read_plus_write": 2 * nbytes / t / 1e9}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 2 GiB device buffer 5 times and print the copy bandwidth "
+                         "(the reference for the HBM traffic counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's multi-GPU "
               "decomposition is described in DESIGN.md but not built", file=sys.stderr)
@@ -129,45 +162,57 @@ def main() -> int:
     n = g.n
     print(f"[bench] generated {W['name']}: nnzb={g.nnzb} in {time.perf_counter() - t_gen:.1f}s",
           file=sys.stderr, flush=True)
+    from paper_1902_07041_amd.autograd import SpringSystem
+
     dev = torch.device("cuda:0")
-    rp = torch.from_numpy(g.row_ptr).to(dev)
-    ci = torch.from_numpy(g.col_idx).to(dev)
-    K = torch.from_numpy(g.blocks).to(dev)
-    m = torch.from_numpy(g.masses).to(dev)
+    k0 = torch.from_numpy(g.k).to(dev)
+    m0 = torch.from_numpy(g.masses).to(dev)
     v0 = torch.from_numpy(gaussian_vector(n, 7)).to(dev)
     X0 = torch.from_numpy(gaussian_block(n, W["block"], 11)).to(dev)
-    Xa = torch.from_numpy(gaussian_block(n, W["adj_block"], 21)).to(dev)
+    Xa0 = torch.from_numpy(gaussian_block(n, W["adj_block"], 21)).to(dev)
     Ya = torch.from_numpy(gaussian_block(n, W["adj_block"], 22)).to(dev)
-    pairs = torch.from_numpy(g.pairs).to(dev)
-    unit = torch.from_numpy(np.ascontiguousarray(g.unit)).to(dev)
+    sysm = SpringSystem(g.row_ptr, g.col_idx, g.pairs, g.unit)
+    h = sysm.h
     torch.cuda.synchronize()
-    h = P.pfe_create(0)
+    stream = torch.cuda.current_stream(dev)     # the library's stream (pfe_create takes torch's)
 
     def step():
         r = {}
+        k = k0.clone().requires_grad_()
+        m = m0.clone().requires_grad_()
+        Xa = Xa0.clone().requires_grad_()
         t0 = time.perf_counter()
-        P.pfe_set_hessian(h, rp, ci, K, m)
+        Hb = sysm.assemble(k, m)
         t1 = time.perf_counter()
         lb, ub, th = P.pfe_estimate_bounds(h, 30, v0)
         t2 = time.perf_counter()
         lo, hi = W["win"][0] * th, W["win"][1] * th
+        f = P.pfe_design_filter(lo, hi, lb, ub, degree=W["degree"])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.pfe_apply_filter(h, f, X0)
+        e1.record(stream)
+        t3 = time.perf_counter()
         o64 = P.pfe_solve_interval(h, lo, hi, W["nev"], W["block"], degree=W["degree"],
                                    tol=W["tol64"], x0=X0, vectors_on_device=True)
-        t3 = time.perf_counter()
+        t4 = time.perf_counter()
         o32 = P.pfe_solve_interval(h, lo, hi, W["nev"], W["block"], degree=W["degree"],
                                    tol=W["tol32"], x0=X0, precision=P.PFE_FP32,
                                    vectors_on_device=True)
-        t4 = time.perf_counter()
-        f = P.pfe_design_filter(lo, hi, lb, ub, degree=W["adj_degree"])
-        dX, dB = P.pfe_apply_filter_adjoint(h, f, Xa, Ya, g.nnzb)
+        t5 = time.perf_counter()
+        fa = P.pfe_design_filter(lo, hi, lb, ub, degree=W["adj_degree"])
+        loss = (Ya * sysm.filter(Xa, Hb, fa)).sum()
+        loss.backward()
         V = o64["evecs"][: W["hf_count"]].contiguous()
         G = P.pfe_eigvec_block_gradient(h, V, g.nnzb)
-        dk, dm = P.pfe_spring_gradient(h, pairs, unit, G, g.n_atoms)
+        dk, dm = P.pfe_spring_gradient(h, sysm.pairs, sysm.unit, G, g.n_atoms)
         torch.cuda.synchronize()
-        t5 = time.perf_counter()
-        r.update(t_hessian=t1 - t0, t_bounds=t2 - t1, t_fp64=t3 - t2, t_fp32=t4 - t3,
-                 t_adjoint=t5 - t4, lam_lb=lb, lam_ub=ub, theta_max=th, lo=lo, hi=hi,
-                 o64=o64, o32=o32, dk=dk, dm=dm, lam_hf=o64["evals"][: W["hf_count"]])
+        t6 = time.perf_counter()
+        r.update(t_hessian=t1 - t0, t_bounds=t2 - t1, t_a4=e0.elapsed_time(e1) / 1e3,
+                 t_fp64=t4 - t3, t_fp32=t5 - t4, t_adjoint=t6 - t5, lam_lb=lb, lam_ub=ub,
+                 theta_max=th, lo=lo, hi=hi, o64=o64, o32=o32, dk=dk, dm=dm,
+                 dk_filter=k.grad, dm_filter=m.grad, lam_hf=o64["evals"][: W["hf_count"]],
+                 a4_degree=f.degree)
         return r
 
     for _ in range(args.warmup):
@@ -184,15 +229,16 @@ def main() -> int:
     def med(key):
         return float(np.median([r[key] for r in res]))
 
-    # dominant kernel: the fused Chebyshev/Clenshaw step of the FP64 solve.
-    # Algorithmic bytes per launch, averaged over one application of degree d:
-    # matrix (values + column indices) and row pointers every launch, and
-    # 4d - 3 multivector streams (2 in the first launch, 3 in the second, 4 after).
-    q, d = W["block"], s64["degree"]
+    # dominant kernel: the fused Chebyshev/Clenshaw step, measured on the a4
+    # application (d launches at q = 96, HIP events on the library's stream).
+    # Algorithmic bytes per launch, averaged over the application: matrix
+    # (values + column indices) and row pointers every launch, and 4d - 3
+    # multivector streams (2 in the first launch, 3 in the second, 4 after).
+    q, d = W["block"], last["a4_degree"]
     mat = g.nnzb * (9 * 8 + 4) + 8 * (g.n_atoms + 1)
     vec = n * q * 8
     bytes_per_launch = mat + vec * (4 * d - 3) / d
-    avg_launch = s64["t_filter"] / s64["filter_steps"]
+    avg_launch = med("t_a4") / d
     achieved = bytes_per_launch / avg_launch / 1e9
     ev64, ev32 = o64["evals"], o32["evals"]
     rel32 = float(np.max(np.abs(ev32 - ev64) / np.abs(ev64))) if ev32.shape == ev64.shape else None
@@ -221,25 +267,33 @@ def main() -> int:
         "t_set_hessian_s": med("t_hessian"),
         "t_bounds_s": med("t_bounds"),
         "t_adjoint_and_gradients_s": med("t_adjoint"),
+        "t_a4_filter_s": med("t_a4"),
         "fp64": {"n_found": int(ev64.size), "iterations": s64["iterations"],
-                 "filter_steps": s64["filter_steps"], "max_resid": float(np.max(o64["resid"])),
-                 "t_filter": s64["t_filter"], "t_orth": s64["t_orth"], "t_rr": s64["t_rr"],
+                 "filter_steps": s64["filter_steps"], "filter_columns": s64["filter_columns"],
+                 "max_resid": float(np.max(o64["resid"])),
+                 "t_filter": s64["t_filter"], "filter_GBps": s64["filter_bytes"] / s64["t_filter"] / 1e9,
+                 "t_orth": s64["t_orth"], "t_rr": s64["t_rr"],
                  "t_resid": s64["t_resid"], "eps": s64["eps"]},
         "fp32_form": {"n_found": int(ev32.size), "iterations": s32["iterations"],
                       "refined": s32["refined"], "filter_steps": s32["filter_steps"],
+                      "filter_columns": s32["filter_columns"],
                       "max_resid": float(np.max(o32["resid"])) if ev32.size else None,
-                      "max_rel_eig_diff_vs_fp64": rel32, "t_filter": s32["t_filter"]},
+                      "max_rel_eig_diff_vs_fp64": rel32, "t_filter": s32["t_filter"],
+                      "filter_GBps": s32["filter_bytes"] / s32["t_filter"] / 1e9},
         "gradients": {"sum_k_dlam_dk_over_sum_lam": float(np.dot(g.k, dk)) / lam_sum,
-                      "sum_m_dlam_dm_over_sum_lam": float(np.dot(g.masses, dm)) / lam_sum},
+                      "sum_m_dlam_dm_over_sum_lam": float(np.dot(g.masses, dm)) / lam_sum,
+                      "filter_loss_grad_norm_k": float(last["dk_filter"].norm()),
+                      "filter_loss_grad_norm_m": float(last["dm_filter"].norm())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(q, d),
-                     "kernel": "k_cheb_tile<double,2,1,2,2> (fused BSR3 Clenshaw step, 2-row tiles)",
+                     "kernel": "k_cheb_tile<double,2,1,2,2> (fused BSR3 Clenshaw step, 2-row tiles), "
+                               "the a4 application's launches",
                      "avg_launch_us": 1e6 * avg_launch,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, (last["lam_lb"], last["lam_ub"]), s64, W)
-    P.pfe_destroy(h)
+    sysm.close()
     print(json.dumps(out))
     return 0
 

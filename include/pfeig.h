@@ -199,6 +199,14 @@ typedef struct {
   const double* x0;    /* optional start block [n][block] (host, or device with
                           PFE_DEVICE_PTRS in flags) */
   uint32_t flags;      /* PFE_DEVICE_PTRS applies to x0 and evecs */
+  int32_t locking;     /* 1 (default): locking of converged Ritz vectors (Sec. 3,
+                          after Algorithm 4): in-window Ritz pairs whose residual
+                          is <= tol/10 are not filtered in the next iteration (the
+                          filter runs on the others, rounded up to a multiple of
+                          8 columns); they stay in the orthonormalisation and in
+                          the Rayleigh-Ritz step, so they keep improving and
+                          rejoin the filtered set if their residual grows.
+                          0: every column is filtered in every iteration. */
 } pfe_solve_opts;
 
 typedef struct {
@@ -217,6 +225,7 @@ typedef struct {
   double gemm_flops;         /* Gram + projection flops */
   double max_resid;          /* largest returned residual */
   int32_t n_window;          /* in-window Ritz values at the end */
+  int64_t filter_columns;    /* sum over iterations of the filtered columns */
 } pfe_solve_stats;
 
 /* Fill opts with defaults (block 0 must then be set by the caller). */

@@ -40,7 +40,7 @@ class CSolveOpts(C.Structure):
     _fields_ = [("block", C.c_int32), ("degree", C.c_int32), ("eps", C.c_double),
                 ("r", C.c_double), ("smoothing", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
-                ("x0", C.c_void_p), ("flags", C.c_uint32)]
+                ("x0", C.c_void_p), ("flags", C.c_uint32), ("locking", C.c_int32)]
 
 
 class CSolveStats(C.Structure):
@@ -49,7 +49,8 @@ class CSolveStats(C.Structure):
                 ("xi", C.c_double), ("eta", C.c_double), ("filter_steps", C.c_int64),
                 ("filter_bytes", C.c_double), ("t_total", C.c_double), ("t_filter", C.c_double),
                 ("t_orth", C.c_double), ("t_rr", C.c_double), ("t_resid", C.c_double),
-                ("gemm_flops", C.c_double), ("max_resid", C.c_double), ("n_window", C.c_int32)]
+                ("gemm_flops", C.c_double), ("max_resid", C.c_double), ("n_window", C.c_int32),
+                ("filter_columns", C.c_int64)]
 
 
 _lib = None
@@ -344,7 +345,7 @@ def pfe_spring_gradient(h, pairs, unit, dblocks, n_atoms: int):
 def pfe_solve_interval(h, lam_lo, lam_hi, nev, block, degree=0, eps=0.0, r=0.0,
                        smoothing=PFE_SMOOTH_NONE, tol=0.0, max_iter=100, precision=PFE_FP64,
                        seed=11, x0=None, want_vectors=True, vectors_on_device=False,
-                       allow_noconv=False):
+                       allow_noconv=False, locking=1):
     """Eigenpairs in [lam_lo, lam_hi].  Returns a dict with evals, evecs
     ([n_found][n], numpy or a GPU tensor), resid, stats, status."""
     L = load_library()
@@ -352,6 +353,7 @@ def pfe_solve_interval(h, lam_lo, lam_hi, nev, block, degree=0, eps=0.0, r=0.0,
     L.pfe_solve_opts_default(C.byref(o))
     o.block, o.degree, o.eps, o.r, o.smoothing = block, degree, eps, r, smoothing
     o.tol, o.max_iter, o.precision, o.seed = tol, max_iter, precision, seed
+    o.locking = locking
     p_x0, dx = _arr(x0, np.float64, "x0")
     o.x0 = p_x0
     o.flags = PFE_DEVICE_PTRS if (dx or vectors_on_device) else 0

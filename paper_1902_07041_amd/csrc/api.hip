@@ -105,11 +105,16 @@ int64_t round_up(int64_t v, int64_t m) { return ((v + m - 1) / m) * m; }
 #endif
 constexpr int kDefaultTileRows = PFE_TILE_ROWS;
 
-// Algorithmic HBM bytes of one Clenshaw step: matrix values and column
-// indices once, row pointers once, and four multivector streams (b_{k+1}
-// gathered once, b_{k+2} and X read, b_k written).
-double step_bytes(int64_t n_atoms, int64_t nnzb, int q, int elem) {
-  return (double)nnzb * (9.0 * elem + 4.0) + 8.0 * (n_atoms + 1) + 4.0 * 3.0 * n_atoms * q * elem;
+// Algorithmic HBM bytes of one filter application of degree d >= 1 by the
+// Clenshaw recurrence (d launches): every launch reads the matrix values,
+// column indices and row pointers once; the multivector streams are 2 in the
+// first launch (X gathered and X), 3 in the second (b_{k+2} = 0 is not read)
+// and 4 after (b_{k+1} gathered once, b_{k+2} and X read, b_k written).
+double filter_bytes(int64_t n_atoms, int64_t nnzb, int q, int elem, int d) {
+  if (d < 1) return 0.0;
+  const double mat = (double)nnzb * (9.0 * elem + 4.0) + 8.0 * (n_atoms + 1);
+  const double vec = 3.0 * n_atoms * q * elem;
+  return d * mat + (4.0 * d - 3.0) * vec;
 }
 
 struct Timer {
@@ -419,6 +424,7 @@ void pfe_solve_opts_default(pfe_solve_opts* o) {
   o->max_iter = 100;
   o->precision = PFE_FP64;
   o->seed = 11;
+  o->locking = 1;
 }
 
 // ----------------------------------------------------------- set_hessian
@@ -842,8 +848,6 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   }
   if (mixed) PFE_TRY(ensure_h32(h, fd.c, fd.e));
   const double bound = 1.05 * coef_abs_sum(fd.coef) + 1e-12;
-  const double sbytes64 = step_bytes(h->n_atoms, h->nnzb, q, 8);
-  const double sbytes32 = step_bytes(h->n_atoms, h->nnzb, q, 4);
   {
     Timer tm(h, &st.t_orth);
     PFE_TRY(cholqr2(h, sm, X, n, q, ld, -1.0));
@@ -856,34 +860,72 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   bool fp64_phase = !mixed;
   double prev_max = HUGE_VAL;
   const pfe::Bsr A = h->bsr();
+  std::vector<int> perm(q);
   for (int it = 1; it <= o.max_iter; ++it) {
+    // Locking: the Ritz vectors of the last Rayleigh-Ritz step that lie in the
+    // window with residual <= tol are not filtered.  The others (rounded up
+    // to a multiple of 8 columns, so the filter keeps its wide aligned loads)
+    // come first; the locked ones follow unfiltered.  Orthonormalisation and
+    // Rayleigh-Ritz act on the span of all q columns.
+    // A pair locks at a tenth of tol: the Rayleigh-Ritz step on the full span
+    // moves a locked vector's residual a little, and one locked just below
+    // tol would cross it again and hold up the stop rule.
+    int nf = q;
+    if (o.locking && !theta.empty() && !(fp64_phase && mixed)) {
+      const double lock_tol = 0.1 * o.tol;
+      auto locked = [&](int j) {
+        return theta[j] >= lam_lo && theta[j] <= lam_hi && res[j] <= lock_tol;
+      };
+      int na = 0;
+      for (int j = 0; j < q; ++j)
+        if (!locked(j)) perm[na++] = j;
+      int nl = na;
+      for (int j = 0; j < q; ++j)
+        if (locked(j)) perm[nl++] = j;
+      nf = std::min<int>(q, (int)round_up(std::max(na, 1), 8));
+    }
     // Y = p(H_hat) X into W (X is read only), then Y is orthonormalised in
     // place and becomes the next basis: the X and W buffers swap roles.
+    // With locked columns, X is first permuted into W, the filter runs from
+    // W's leading nf columns into X, and the locked columns are copied after
+    // them; then no swap is needed.
+    double* Fin = X;
+    double* Fout = W;
+    if (nf < q) {
+      PFE_HIP(hipMemcpyAsync(sm.sel, perm.data(), q * sizeof(int), hipMemcpyHostToDevice, h->stream));
+      PFE_HIP(pfe::permute_cols_f64(n, q, X, ld, sm.sel, W, h->stream));
+      PFE_HIP(pfe::copy_cols_f64(n, q - nf, W + nf, ld, X + nf, ld, h->stream));
+      Fin = W;
+      Fout = X;
+    }
+    st.filter_columns += nf;
     if (fp64_phase) {
       Timer tm(h, &st.t_filter);
-      PFE_TRY(run_filter<double>(h, h->step_vals64(), fd.coef, 1.0 / fd.e, -fd.c / fd.e, X, W,
-                                 (double*)R, q, ld, &st.filter_steps));
-      st.filter_bytes += sbytes64 * fd.degree;
+      PFE_TRY(run_filter<double>(h, h->step_vals64(), fd.coef, 1.0 / fd.e, -fd.c / fd.e, Fin, Fout,
+                                 (double*)R, nf, ld, &st.filter_steps));
+      st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 8, fd.degree);
       st.fp64_iterations++;
     } else {
       float* X32 = (float*)R;
       float* P32 = X32 + n * ld;
       float* Q32 = P32 + n * ld;
       Timer tm(h, &st.t_filter);
-      PFE_HIP(pfe::cast_f64_to_f32(n, q, X, ld, X32, ld, h->stream));
-      PFE_TRY(run_filter<float>(h, h->H32.as<float>(), fd.coef, 1.0, 0.0, X32, P32, Q32, q, ld,
+      PFE_HIP(pfe::cast_f64_to_f32(n, nf, Fin, ld, X32, ld, h->stream));
+      PFE_TRY(run_filter<float>(h, h->H32.as<float>(), fd.coef, 1.0, 0.0, X32, P32, Q32, nf, ld,
                                 &st.filter_steps));
-      PFE_HIP(pfe::cast_f32_to_f64(n, q, P32, ld, W, ld, h->stream));
-      st.filter_bytes += sbytes32 * fd.degree;
+      PFE_HIP(pfe::cast_f32_to_f64(n, nf, P32, ld, Fout, ld, h->stream));
+      st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 4, fd.degree);
     }
     {
       Timer tm(h, &st.t_orth);
-      PFE_TRY(cholqr2(h, sm, W, n, q, ld, bound));
+      PFE_TRY(cholqr2(h, sm, Fout, n, q, ld, bound));
     }
-    std::swap(h->wsA.p, h->wsB.p);
-    std::swap(h->wsA.bytes, h->wsB.bytes);
-    X = h->wsA.as<double>();
-    W = h->wsB.as<double>();
+    if (Fout == W) {
+      std::swap(h->wsA.p, h->wsB.p);
+      std::swap(h->wsA.bytes, h->wsB.bytes);
+      X = h->wsA.as<double>();
+      W = h->wsB.as<double>();
+    }
     PFE_TRY(rayleigh_ritz(h, sm, X, W, n, q, ld, theta, res, &st.t_rr, &st.t_resid));
     st.iterations = it;
     int cnt = 0;

@@ -172,6 +172,9 @@ hipError_t cast_f32_to_f64(int64_t n, int q, const float* X, int64_t ldx, double
 // Y[:, :q] = X[:, :q] (any lds)
 hipError_t copy_cols_f64(int64_t n, int q, const double* X, int64_t ldx, double* Y, int64_t ldy,
                          hipStream_t s);
+// Y[:, c] = X[:, perm[c]] (perm a device array of q column indices; X != Y).
+hipError_t permute_cols_f64(int64_t n, int q, const double* X, int64_t ld, const int* perm,
+                            double* Y, hipStream_t s);
 hipError_t zero_f64(double* p, int64_t count, hipStream_t s);
 hipError_t zero_f32(float* p, int64_t count, hipStream_t s);
 // Standard normal entries for X[r][c], r < n, c < q, from Philox4x32-10

@@ -528,6 +528,14 @@ __global__ void k_copy_cols(int64_t n, int q, const double* __restrict__ X, int6
   const int64_t r = i / q, c = i % q;
   Y[r * ldy + c] = X[r * ldx + c];
 }
+// Y[:, c] = X[:, perm[c]] for c < q (column permutation of a row-major block).
+__global__ void k_permute_cols(int64_t n, int q, const double* __restrict__ X, int64_t ld,
+                               const int* __restrict__ perm, double* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * q) return;
+  const int64_t r = i / q, c = i % q;
+  Y[r * ld + c] = X[r * ld + perm[c]];
+}
 template <typename T>
 __global__ void k_zero(T* p, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -820,6 +828,12 @@ hipError_t copy_cols_f64(int64_t n, int q, const double* X, int64_t ldx, double*
                          hipStream_t s) {
   if (n * q == 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_cols, dim3(nblocks(n * q, 256)), dim3(256), 0, s, n, q, X, ldx, Y, ldy);
+  return hipGetLastError();
+}
+hipError_t permute_cols_f64(int64_t n, int q, const double* X, int64_t ld, const int* perm,
+                            double* Y, hipStream_t s) {
+  if (n * q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute_cols, dim3(nblocks(n * q, 256)), dim3(256), 0, s, n, q, X, ld, perm, Y);
   return hipGetLastError();
 }
 hipError_t zero_f64(double* p, int64_t count, hipStream_t s) {

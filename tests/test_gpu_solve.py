@@ -62,6 +62,29 @@ def test_solve_fp64_matches_oracle_si(case):
     np.testing.assert_allclose(out["evals"], th, rtol=1e-10)
 
 
+@pytest.mark.parametrize("prec,tol", [(P.PFE_FP64, 1e-10), (P.PFE_FP32, 1e-8)])
+def test_solve_locking_same_pairs_fewer_columns(case, prec, tol):
+    """Locking of converged Ritz vectors (Sec. 3, after Algorithm 4) returns the
+    same eigenpairs while filtering fewer columns."""
+    banner(f"solve locking on/off precision={prec}")
+    X0 = gaussian_block(case.n, 32, 11)
+    runs = {}
+    for lk in (0, 1):
+        out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=tol,
+                                   precision=prec, x0=X0, locking=lk)
+        assert out["status"] == "PFE_OK", out["stats"]
+        check_pairs(case, out, tol, max(tol, 1e-9))
+        runs[lk] = out["stats"]
+    full = runs[0]["filter_columns"]
+    assert full == 32 * runs[0]["iterations"]
+    if prec == P.PFE_FP64:
+        assert runs[1]["filter_columns"] < 32 * runs[1]["iterations"]
+    else:
+        # FP32 residuals stall above tol, so nothing locks before the FP64
+        # sweep, which filters every column
+        assert runs[1]["filter_columns"] <= 32 * runs[1]["iterations"]
+
+
 def test_solve_fp32_form(case):
     banner("solve fp32-filter form N=1000")
     X0 = gaussian_block(case.n, 32, 11)

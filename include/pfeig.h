@@ -241,12 +241,55 @@ void pfe_solve_opts_default(pfe_solve_opts* opts);
  * ||H v - lambda v|| / lam_ub (host, may be NULL), stats (may be NULL).
  * Stops when every Ritz value within 1e-6 lam_ub of the window has a
  * residual <= tol in two consecutive iterations with the same in-window
- * count (and at least three iterations have run).  ECAPACITY: *n_found = number of in-window Ritz values (> nev),
- * nothing else written.  ENOCONV: the converged in-window pairs are
+ * count (and at least three iterations have run).  ECAPACITY: *n_found = number of in-window Ritz values, which
+ * exceeds nev, or equals the block (every Ritz value in the window, so the
+ * block cannot show the count is complete); nothing else written.  ENOCONV: the converged in-window pairs are
  * returned. */
 pfe_status pfe_solve_interval(pfe_handle h, double lam_lo, double lam_hi, int32_t nev,
                               const pfe_solve_opts* opts, int32_t* n_found, double* evals,
                               double* evecs, double* resid, pfe_solve_stats* stats);
+
+/* Spectrum slicing (end of Sec. 2.6; Sec. 6): eigenpairs in [lam_lo, lam_hi]
+ * when they do not fit one subspace.  The window is cut into sub-windows
+ * (explicit cuts, or where the count estimate of eq. eigval_count_estimator
+ * from pfe_count_moments reaches equal shares), each solved like
+ * pfe_solve_interval with opts (block, r, smoothing, tol, max_iter, precision,
+ * locking, seed; degree, eps and x0 are ignored) and a filter margin of
+ * `margin` times its width (degree by eq. thresh).  Interior cuts are widened
+ * by 1e-8 lam_ub on both sides; pairs within that guard are grouped by
+ * eigenvalue (a gap above 1e-9 lam_ub starts a new group) and each group is
+ * taken from the side that found more of it, so no pair is lost or returned
+ * twice, also for degenerate eigenvalues on a cut.  A sub-window that returns
+ * ECAPACITY or ENOCONV is split in two (up to 64 splits).
+ * Outputs as pfe_solve_interval (evecs [nev][n], host or device by
+ * opts->flags), plus the number of sub-windows used and their boundaries
+ * cuts[n_slices + 1] (host, if cuts_cap is large enough).  Needs device
+ * memory for nev + block eigenvectors. */
+typedef struct {
+  int32_t n_slices;       /* sub-windows; 0: ceil(estimated count / per_slice) */
+  int32_t per_slice;      /* eigenvalues aimed for per sub-window (0: block / 2) */
+  double margin;          /* filter margin / sub-window width (0: 1/6) */
+  int32_t count_degree;   /* Jackson-damped series degree of the count (0: 1000) */
+  int32_t count_samples;  /* probe vectors of the count (0: 32) */
+  uint64_t count_seed;    /* probe vector seed */
+  const double* cuts;     /* optional interior cuts [n_slices - 1] (host), ascending */
+} pfe_slice_opts;
+
+pfe_status pfe_solve_sliced(pfe_handle h, double lam_lo, double lam_hi, int32_t nev,
+                            const pfe_solve_opts* opts, const pfe_slice_opts* slice_opts,
+                            int32_t* n_found, double* evals, double* evecs, double* resid,
+                            int32_t* n_slices, double* cuts, int32_t cuts_cap,
+                            pfe_solve_stats* stats);
+
+/* Chebyshev moments of the spectral density seen by M = nsamples unit probe
+ * vectors (V [n][M] row-major if given, else drawn by the library from seed):
+ * mu_k = (1/M) sum_l v_l^T T_k(H_hat) v_l for k = 0..K (host output
+ * mu[K+1]), H_hat = (H - c I)/e from the stored bounds.  The count estimate
+ * of eq. eigval_count_estimator for any window is n sum_k g_k gamma_k mu_k
+ * with the window's characteristic-function coefficients gamma_k and damping
+ * g_k. */
+pfe_status pfe_count_moments(pfe_handle h, int32_t K, int32_t nsamples, const double* V,
+                             uint64_t seed, uint32_t flags, double* mu);
 
 /* Stochastic estimate of the number of eigenvalues in [lam_lo, lam_hi]
  * (Sec. 2.4, eq. eigval_count_estimator): (n/M) sum_l v_l^T psi(H_hat) v_l

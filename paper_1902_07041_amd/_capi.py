@@ -43,6 +43,12 @@ class CSolveOpts(C.Structure):
                 ("x0", C.c_void_p), ("flags", C.c_uint32), ("locking", C.c_int32)]
 
 
+class CSliceOpts(C.Structure):
+    _fields_ = [("n_slices", C.c_int32), ("per_slice", C.c_int32), ("margin", C.c_double),
+                ("count_degree", C.c_int32), ("count_samples", C.c_int32), ("count_seed", C.c_uint64),
+                ("cuts", C.c_void_p)]
+
+
 class CSolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("fp64_iterations", C.c_int32), ("refined", C.c_int32),
                 ("degree", C.c_int32), ("eps", C.c_double), ("c", C.c_double), ("e", C.c_double),
@@ -104,10 +110,14 @@ def load_library():
     L.pfe_solve_interval.argtypes = [vp, dbl, dbl, i32, C.POINTER(CSolveOpts), C.POINTER(i32), vp,
                                      vp, vp, C.POINTER(CSolveStats)]
     L.pfe_estimate_count.argtypes = [vp, dbl, dbl, i32, i32, i32, vp, u64, u32, pd]
+    L.pfe_solve_sliced.argtypes = [vp, dbl, dbl, i32, C.POINTER(CSolveOpts), C.POINTER(CSliceOpts),
+                                   C.POINTER(i32), vp, vp, vp, C.POINTER(i32), vp, i32,
+                                   C.POINTER(CSolveStats)]
+    L.pfe_count_moments.argtypes = [vp, i32, i32, vp, u64, u32, vp]
     for name in ("pfe_create", "pfe_set_hessian", "pfe_set_springs", "pfe_estimate_bounds", "pfe_set_bounds",
                  "pfe_design_filter", "pfe_apply_filter", "pfe_apply_filter_adjoint",
                  "pfe_eigvec_block_gradient", "pfe_spring_gradient", "pfe_solve_interval",
-                 "pfe_estimate_count"):
+                 "pfe_estimate_count", "pfe_solve_sliced", "pfe_count_moments"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -383,6 +393,65 @@ def pfe_solve_interval(h, lam_lo, lam_hi, nev, block, degree=0, eps=0.0, r=0.0,
     sd = {f: getattr(stats, f) for f, _ in CSolveStats._fields_}
     return {"evals": ev[:k].copy(), "evecs": None if vecs is None else vecs[:k],
             "resid": rs[:k].copy(), "stats": sd, "status": STATUS.get(st, st)}
+
+
+def pfe_solve_sliced(h, lam_lo, lam_hi, nev, block, n_slices=0, per_slice=0, margin=0.0,
+                     count_degree=0, count_samples=0, count_seed=13, cuts=None, r=0.0,
+                     smoothing=PFE_SMOOTH_NONE, tol=0.0, max_iter=100, precision=PFE_FP64, seed=11,
+                     locking=1, want_vectors=True, vectors_on_device=False):
+    """Eigenpairs in [lam_lo, lam_hi] by spectrum slicing.  Returns a dict with
+    evals, evecs ([n_found][n]), resid, stats, status, n_slices and the
+    sub-window boundaries."""
+    L = load_library()
+    o = CSolveOpts()
+    L.pfe_solve_opts_default(C.byref(o))
+    o.block, o.r, o.smoothing, o.tol, o.max_iter = block, r, smoothing, tol, max_iter
+    o.precision, o.seed, o.locking = precision, seed, locking
+    o.flags = PFE_DEVICE_PTRS if vectors_on_device else 0
+    so = CSliceOpts()
+    so.n_slices, so.per_slice, so.margin = n_slices, per_slice, margin
+    so.count_degree, so.count_samples, so.count_seed = count_degree, count_samples, count_seed
+    cuts_arr = None
+    if cuts is not None:
+        cuts_arr = np.ascontiguousarray(cuts, dtype=np.float64)
+        so.n_slices = cuts_arr.size + 1
+        so.cuts = cuts_arr.ctypes.data
+    n_found = C.c_int32()
+    ns = C.c_int32()
+    ev = np.zeros(max(nev, 1))
+    rs = np.zeros(max(nev, 1))
+    cut_out = np.zeros(4098)
+    stats = CSolveStats()
+    vecs = None
+    p_vec = None
+    if want_vectors and nev > 0 and h.value in _N:
+        n = _n_of(h)
+        if vectors_on_device:
+            import torch
+            vecs = torch.zeros((nev, n), dtype=torch.float64, device="cuda")
+            p_vec = vecs.data_ptr()
+        else:
+            vecs = np.zeros((nev, n))
+            p_vec = vecs.ctypes.data
+    st = L.pfe_solve_sliced(h, lam_lo, lam_hi, nev, C.byref(o), C.byref(so), C.byref(n_found),
+                            ev.ctypes.data, p_vec, rs.ctypes.data, C.byref(ns), cut_out.ctypes.data,
+                            cut_out.size, C.byref(stats))
+    _check(h, st)
+    k = n_found.value
+    sd = {f: getattr(stats, f) for f, _ in CSolveStats._fields_}
+    return {"evals": ev[:k].copy(), "evecs": None if vecs is None else vecs[:k],
+            "resid": rs[:k].copy(), "stats": sd, "status": STATUS.get(st, st),
+            "n_slices": ns.value, "cuts": cut_out[: ns.value + 1].copy()}
+
+
+def pfe_count_moments(h, K: int, nsamples: int = 32, V=None, seed: int = 13):
+    """mu_k = (1/M) sum_l v_l^T T_k(H_hat) v_l, k = 0..K (numpy)."""
+    L = load_library()
+    p_v, dv = _arr(V, np.float64, "V")
+    mu = np.zeros(K + 1)
+    _check(h, L.pfe_count_moments(h, K, nsamples, p_v, seed, PFE_DEVICE_PTRS if dv else 0,
+                                  mu.ctypes.data))
+    return mu
 
 
 def _n_of(h) -> int:

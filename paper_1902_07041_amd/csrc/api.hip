@@ -42,6 +42,7 @@ struct pfe_ctx {
   DevBuf wsRed;                 // reduction partials
   DevBuf wsOut;                 // eigenvector output staging
   DevBuf wsCk;                  // adjoint checkpoints
+  DevBuf wsSlice;               // eigenvectors collected over the slices of a sliced solve
   hipEvent_t ev[2] = {nullptr, nullptr};
 
   pfe::Bsr bsr() const {
@@ -409,7 +410,7 @@ int64_t pfe_device_bytes(pfe_handle h) {
   const DevBuf* bufs[] = {&h->tile_ptr, &h->tile_vptr, &h->tile_cm, &h->tile_perm, &h->Ht,
                           &h->row_ptr, &h->col_idx, &h->H,    &h->transpose, &h->masses,
                           &h->H32,     &h->flags,   &h->wsA,  &h->wsB,       &h->wsC,
-                          &h->wsD,     &h->wsSmall, &h->wsRed, &h->wsOut,    &h->wsCk};
+                          &h->wsD,     &h->wsSmall, &h->wsRed, &h->wsOut,    &h->wsCk, &h->wsSlice};
   int64_t s = 0;
   for (auto* b : bufs) s += (int64_t)b->bytes;
   return s;
@@ -976,6 +977,12 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     *n_found = total_in;
     return pfe::fail(PFE_ECAPACITY, "more eigenvalues in the window than nev");
   }
+  if (total_in >= q && q < n) {
+    // every Ritz value lies in the window: the subspace cannot show that the
+    // window holds no more eigenvalues (Sec. 2.6 asks q above the count)
+    *n_found = total_in;
+    return pfe::fail(PFE_ECAPACITY, "block too small: every Ritz value lies in the window");
+  }
   const int ns = (int)sel.size();
   *n_found = ns;
   double maxr = 0;
@@ -1066,6 +1073,342 @@ pfe_status pfe_estimate_count(pfe_handle h, double lam_lo, double lam_hi, int32_
   if (!h) return PFE_EINVAL;
   return finish(h, count_impl(h, lam_lo, lam_hi, degree, smoothing, nsamples, V, seed, flags,
                               count));
+}
+
+// ---------------------------------------------------------------- moments
+// mu_k = (1/M) sum_l v_l^T T_k(H_hat) v_l, k = 0..K, for M unit probe vectors,
+// by the three-term recurrence (eq. 3-term-recurrence) with one column-dot
+// reduction per step.  Any window's count estimate of eq.
+// eigval_count_estimator is then n sum_k chi_k mu_k.
+static Err moments_impl(pfe_handle h, int K, int M, const double* V, uint64_t seed, uint32_t flags,
+                        std::vector<double>* mu) {
+  PFE_TRY(select_device(h));
+  if (!h->has_h) return pfe::fail(PFE_ESTATE, "no Hessian set");
+  if (!h->has_bounds) return pfe::fail(PFE_ESTATE, "no spectral bounds");
+  if (K < 0 || K > 100000 || M < 1 || M > 256) return pfe::fail(PFE_EINVAL, "need 0 <= K <= 100000, 1 <= nsamples <= 256");
+  const int64_t n = h->n();
+  const double c = 0.5 * (h->lam_ub + h->lam_lb), e = 0.5 * (h->lam_ub - h->lam_lb);
+  const int64_t ld = round_up(M, 8);
+  const size_t mv = (size_t)n * ld * sizeof(double);
+  PFE_HIP(h->wsA.ensure(mv));
+  PFE_HIP(h->wsB.ensure(mv));
+  PFE_HIP(h->wsC.ensure(mv));
+  double* Vd = h->wsA.as<double>();
+  double* Ta = h->wsB.as<double>();
+  double* Tb = h->wsC.as<double>();
+  PFE_HIP(pfe::zero_f64(Vd, n * ld, h->stream));
+  if (V) {
+    if (flags & PFE_DEVICE_PTRS) {
+      PFE_HIP(pfe::copy_cols_f64(n, M, V, M, Vd, ld, h->stream));
+    } else {
+      PFE_HIP(hipMemcpy2DAsync(Vd, ld * sizeof(double), V, M * sizeof(double), M * sizeof(double),
+                               n, hipMemcpyHostToDevice, h->stream));
+    }
+  } else {
+    PFE_HIP(pfe::gaussian_fill_f64(n, M, Vd, ld, seed, h->stream));
+  }
+  PFE_TRY(ensure_red(h, n, M));
+  PFE_HIP(h->wsSmall.ensure((size_t)(M + (int64_t)(K + 1) * M) * sizeof(double) + 64));
+  double* nrm = h->wsSmall.as<double>();
+  double* dots = nrm + M;
+  PFE_HIP(pfe::col_norms_f64(n, M, Vd, ld, nrm, h->wsRed.p, h->stream));
+  PFE_HIP(pfe::col_scale_inv_f64(n, M, Vd, ld, nrm, h->stream));
+  const pfe::Bsr A = h->bsr();
+  const double* Hv = h->step_vals64();
+  const double a1 = 1.0 / e, b1 = -c / e;
+  PFE_HIP(pfe::col_dots_f64(n, M, Vd, Vd, ld, dots, h->wsRed.p, h->stream));
+  if (K >= 1) {
+    PFE_HIP(pfe::cheb_step_f64(A, Hv, Vd, nullptr, nullptr, Ta, M, ld, a1, b1, 0.0, 0.0, h->stream));
+    PFE_HIP(pfe::col_dots_f64(n, M, Vd, Ta, ld, dots + M, h->wsRed.p, h->stream));
+  }
+  // t_{k+1} = 2 H_hat t_k - t_{k-1}, written over t_{k-1}
+  const double* tprev = Vd;
+  double* tcur = Ta;
+  double* spare = Tb;
+  for (int k = 1; k < K; ++k) {
+    double* tnext = (tprev == Vd) ? spare : const_cast<double*>(tprev);
+    PFE_HIP(pfe::cheb_step_f64(A, Hv, tcur, tprev, nullptr, tnext, M, ld, 2.0 * a1, 2.0 * b1, -1.0,
+                               0.0, h->stream));
+    PFE_HIP(pfe::col_dots_f64(n, M, Vd, tnext, ld, dots + (int64_t)(k + 1) * M, h->wsRed.p, h->stream));
+    tprev = tcur;
+    tcur = tnext;
+  }
+  std::vector<double> hd((size_t)(K + 1) * M);
+  PFE_HIP(hipMemcpyAsync(hd.data(), dots, hd.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  PFE_TRY(sync(h));
+  mu->assign(K + 1, 0.0);
+  for (int k = 0; k <= K; ++k) {
+    double sm = 0;
+    for (int l = 0; l < M; ++l) sm += hd[(size_t)k * M + l];
+    (*mu)[k] = sm / M;
+  }
+  return pfe::ok();
+}
+
+pfe_status pfe_count_moments(pfe_handle h, int32_t K, int32_t nsamples, const double* V,
+                             uint64_t seed, uint32_t flags, double* mu) {
+  if (!h) return PFE_EINVAL;
+  if (!mu) return finish(h, pfe::fail(PFE_EINVAL, "mu output required"));
+  std::vector<double> m;
+  Err e = moments_impl(h, K, nsamples, V, seed, flags, &m);
+  if (e.st == PFE_OK) std::copy(m.begin(), m.end(), mu);
+  return finish(h, e);
+}
+
+// ---------------------------------------------------------------- slicing
+// Spectrum slicing (end of Sec. 2.6; Sec. 6): [lam_lo, lam_hi] is cut where
+// the moment-based count estimate reaches equal shares, every sub-window is
+// solved by the filtered subspace iteration with a margin proportional to its
+// width (degree by eq. thresh), and the results are merged.  Interior cuts get
+// a guard g on both sides, so an eigenvalue near a cut is found by both
+// neighbours; there the pairs are grouped by eigenvalue (gap > tau starts a
+// new group) and each group is taken from the side that found more of it,
+// which removes duplicates also for degenerate clusters.  A sub-window that
+// overflows the block or does not converge is split in two.
+static Err sliced_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
+                       const pfe_solve_opts* o_in, const pfe_slice_opts* so_in, int* n_found,
+                       double* evals, double* evecs, double* resid, int* n_slices_out,
+                       double* cuts_out, int cuts_cap, pfe_solve_stats* st_out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  PFE_TRY(select_device(h));
+  if (!h->has_h) return pfe::fail(PFE_ESTATE, "no Hessian set");
+  if (!h->has_bounds) return pfe::fail(PFE_ESTATE, "no spectral bounds (estimate_bounds or set_bounds)");
+  pfe_solve_opts o;
+  pfe_solve_opts_default(&o);
+  if (o_in) o = *o_in;
+  pfe_slice_opts so;
+  std::memset(&so, 0, sizeof(so));
+  so.count_seed = 13;
+  if (so_in) so = *so_in;
+  const int q = o.block;
+  const int64_t n = h->n();
+  if (q < 1 || q > 256 || q > n) return pfe::fail(PFE_EINVAL, "block must be in [1, min(256, n)]");
+  if (nev < 0 || !n_found) return pfe::fail(PFE_EINVAL, "nev >= 0 and n_found required");
+  if (!(lam_lo < lam_hi) || lam_lo < h->lam_lb || lam_hi > h->lam_ub)
+    return pfe::fail(PFE_EINVAL, "window must satisfy lam_lb <= lam_lo < lam_hi <= lam_ub");
+  if (so.n_slices < 0 || so.per_slice < 0 || so.margin < 0 || so.count_degree < 0 || so.count_samples < 0)
+    return pfe::fail(PFE_EINVAL, "slice options must be >= 0");
+  const double margin = so.margin > 0 ? so.margin : 1.0 / 6.0;
+  const int per = so.per_slice > 0 ? so.per_slice : std::max(1, q / 2);
+  const int K = so.count_degree > 0 ? so.count_degree : 1000;
+  const int M = so.count_samples > 0 ? so.count_samples : 32;
+  const double c = 0.5 * (h->lam_ub + h->lam_lb), e = 0.5 * (h->lam_ub - h->lam_lb);
+  const double g = 1e-8 * h->lam_ub;
+  const double tau = 1e-9 * h->lam_ub;
+  // ---- cut points
+  std::vector<double> mu;
+  auto count_to = [&](double x) {
+    const std::vector<double> chi =
+        pfe::chi_coefficients((lam_lo - c) / e, (x - c) / e, K, PFE_SMOOTH_JACKSON);
+    double acc = 0;
+    for (int k = 0; k <= K; ++k) acc += chi[k] * mu[k];
+    return (double)n * acc;
+  };
+  std::vector<double> bnd{lam_lo};
+  if (so.cuts && so.n_slices > 1) {
+    for (int i = 0; i < so.n_slices - 1; ++i) {
+      const double x = so.cuts[i];
+      if (!(x > bnd.back() && x < lam_hi)) return pfe::fail(PFE_EINVAL, "cuts must increase strictly inside the window");
+      bnd.push_back(x);
+    }
+  } else if (so.n_slices != 1) {
+    PFE_TRY(moments_impl(h, K, M, nullptr, so.count_seed, 0, &mu));
+    const double total = count_to(lam_hi);
+    int ns = so.n_slices > 0 ? so.n_slices : std::max(1, (int)std::ceil(total / per));
+    ns = std::min(ns, 4096);
+    if (ns > 1) {
+      const int G = 4096;
+      std::vector<double> xs(G + 1), Ns(G + 1);
+      for (int i = 0; i <= G; ++i) {
+        xs[i] = lam_lo + (lam_hi - lam_lo) * i / G;
+        Ns[i] = i == 0 ? 0.0 : std::max(Ns[i - 1], count_to(xs[i]));
+      }
+      int gi = 1;
+      for (int i = 1; i < ns; ++i) {
+        const double target = Ns[G] * i / ns;
+        while (gi < G && Ns[gi] < target) ++gi;
+        const double f = (Ns[gi] > Ns[gi - 1]) ? (target - Ns[gi - 1]) / (Ns[gi] - Ns[gi - 1]) : 0.5;
+        const double x = xs[gi - 1] + f * (xs[gi] - xs[gi - 1]);
+        if (x > bnd.back() + 1e-6 * (lam_hi - lam_lo) && x < lam_hi - 1e-6 * (lam_hi - lam_lo))
+          bnd.push_back(x);
+      }
+    }
+  }
+  bnd.push_back(lam_hi);
+  // ---- slices, lowest first; a failed slice is replaced by its two halves
+  std::vector<std::pair<double, double>> todo;
+  for (size_t i = bnd.size() - 1; i >= 1; --i) todo.emplace_back(bnd[i - 1], bnd[i]);
+  struct Pair {
+    double th, res;
+  };
+  std::vector<Pair> kept;                  // ascending; vector i in slot i of VB
+  const int cap = nev + q;
+  PFE_HIP(h->wsSlice.ensure((size_t)cap * n * sizeof(double)));
+  double* VB = h->wsSlice.as<double>();
+  pfe_solve_stats agg;
+  std::memset(&agg, 0, sizeof(agg));
+  std::vector<double> used{lam_lo};
+  int splits = 0, slice_no = 0;
+  std::vector<double> ev(q), rs(q);
+  while (!todo.empty()) {
+    const double a = todo.back().first, b = todo.back().second;
+    todo.pop_back();
+    const bool first = a == lam_lo, last = b == lam_hi;
+    const double wa = first ? a : std::max(h->lam_lb, a - g);
+    const double wb = last ? b : std::min(h->lam_ub, b + g);
+    pfe_solve_opts os = o;
+    os.degree = 0;
+    os.eps = margin * (wb - wa) / e;
+    os.x0 = nullptr;
+    os.seed = o.seed + 7919ull * (uint64_t)slice_no;
+    os.flags = PFE_DEVICE_PTRS;
+    const int base = (int)kept.size();
+    if (base + q > cap) {
+      *n_found = base;
+      return pfe::fail(PFE_ECAPACITY, "more eigenvalues in the window than nev");
+    }
+    int nf = 0;
+    pfe_solve_stats ss;
+    std::memset(&ss, 0, sizeof(ss));
+    const Err r = solve_impl(h, wa, wb, q, &os, &nf, ev.data(), VB + (size_t)base * n, rs.data(), &ss);
+    ++slice_no;
+    agg.iterations += ss.iterations;
+    agg.fp64_iterations += ss.fp64_iterations;
+    agg.refined += ss.refined;
+    agg.degree = std::max(agg.degree, ss.degree);
+    agg.filter_steps += ss.filter_steps;
+    agg.filter_bytes += ss.filter_bytes;
+    agg.filter_columns += ss.filter_columns;
+    agg.t_filter += ss.t_filter;
+    agg.t_orth += ss.t_orth;
+    agg.t_rr += ss.t_rr;
+    agg.t_resid += ss.t_resid;
+    agg.c = ss.c;
+    agg.e = ss.e;
+    if (r.st == PFE_ECAPACITY || r.st == PFE_ENOCONV) {
+      // too many eigenvalues for the block, or no convergence: halve the
+      // sub-window
+      if (++splits > 64 || (b - a) < 1e-6 * (lam_hi - lam_lo))
+        return pfe::fail(r.st, "sub-window [" + std::to_string(a) + ", " + std::to_string(b) +
+                                   "] failed after splitting: " + r.msg);
+      double mid = 0.5 * (a + b);
+      if (!mu.empty()) {
+        const double na = count_to(a), nb = count_to(b);
+        if (nb - na > 1.0) {
+          double lo2 = a, hi2 = b;
+          for (int it = 0; it < 40; ++it) {
+            const double m2 = 0.5 * (lo2 + hi2);
+            (count_to(m2) < 0.5 * (na + nb) ? lo2 : hi2) = m2;
+          }
+          const double cand = 0.5 * (lo2 + hi2);
+          if (cand > a + 0.05 * (b - a) && cand < b - 0.05 * (b - a)) mid = cand;
+        }
+      }
+      todo.emplace_back(mid, b);
+      todo.emplace_back(a, mid);
+      continue;
+    }
+    if (r) return r;
+    used.push_back(b);
+    // merge the pairs near the cut a: old ones (end of `kept`) and new ones
+    std::vector<int> order;          // final sequence of (negative: old slot, else new index)
+    int zone0 = base;
+    if (!first) {
+      while (zone0 > 0 && kept[zone0 - 1].th >= a - g) --zone0;
+    }
+    struct Z {
+      double th;
+      int src;   // 0 old, 1 new
+      int idx;
+    };
+    std::vector<Z> z;
+    for (int i = zone0; i < base; ++i) z.push_back({kept[i].th, 0, i});
+    int nz_new = 0;
+    if (!first)
+      while (nz_new < nf && ev[nz_new] <= a + g) ++nz_new;
+    for (int i = 0; i < nz_new; ++i) z.push_back({ev[i], 1, i});
+    std::stable_sort(z.begin(), z.end(), [](const Z& x, const Z& y) { return x.th < y.th; });
+    std::vector<char> keep(z.size(), 1);
+    for (size_t g0 = 0; g0 < z.size();) {
+      size_t g1 = g0 + 1;
+      while (g1 < z.size() && z[g1].th - z[g1 - 1].th <= tau) ++g1;
+      int c0 = 0, c1 = 0;
+      for (size_t i = g0; i < g1; ++i) (z[i].src ? c1 : c0)++;
+      if (c0 > 0 && c1 > 0) {
+        const int drop = (c1 > c0) ? 0 : 1;
+        for (size_t i = g0; i < g1; ++i)
+          if (z[i].src == drop) keep[i] = 0;
+      }
+      g0 = g1;
+    }
+    // new layout from slot zone0: kept zone entries in theta order, then the
+    // remaining new pairs
+    std::vector<std::pair<int, Pair>> seq;   // (source slot, pair)
+    for (size_t i = 0; i < z.size(); ++i)
+      if (keep[i]) {
+        if (z[i].src == 0)
+          seq.push_back({z[i].idx, kept[z[i].idx]});
+        else
+          seq.push_back({base + z[i].idx, Pair{ev[z[i].idx], rs[z[i].idx]}});
+      }
+    for (int i = nz_new; i < nf; ++i) seq.push_back({base + i, Pair{ev[i], rs[i]}});
+    // sources are not in ascending slot order inside the zone (old and new
+    // interleave by theta): stage through wsOut when any move is out of order
+    bool monotone = true;
+    for (size_t i = 1; i < seq.size(); ++i) monotone = monotone && seq[i].first > seq[i - 1].first;
+    if (!monotone) {
+      PFE_HIP(h->wsOut.ensure(seq.size() * (size_t)n * sizeof(double)));
+      double* tmp = h->wsOut.as<double>();
+      for (size_t i = 0; i < seq.size(); ++i)
+        PFE_HIP(hipMemcpyAsync(tmp + i * (size_t)n, VB + (size_t)seq[i].first * n, n * sizeof(double),
+                               hipMemcpyDeviceToDevice, h->stream));
+      PFE_HIP(hipMemcpyAsync(VB + (size_t)zone0 * n, tmp, seq.size() * (size_t)n * sizeof(double),
+                             hipMemcpyDeviceToDevice, h->stream));
+    } else {
+      for (size_t i = 0; i < seq.size(); ++i) {
+        const int dst = zone0 + (int)i;
+        if (dst != seq[i].first)
+          PFE_HIP(hipMemcpyAsync(VB + (size_t)dst * n, VB + (size_t)seq[i].first * n,
+                                 n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+      }
+    }
+    kept.resize(zone0);
+    for (auto& sp : seq) kept.push_back(sp.second);
+  }
+  PFE_TRY(sync(h));
+  const int total = (int)kept.size();
+  agg.n_window = total;
+  for (auto& kp : kept) agg.max_resid = std::max(agg.max_resid, kp.res);
+  if (n_slices_out) *n_slices_out = (int)used.size() - 1;
+  if (cuts_out && cuts_cap >= (int)used.size())
+    std::copy(used.begin(), used.end(), cuts_out);
+  agg.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st_out) *st_out = agg;
+  *n_found = total;
+  if (total > nev) return pfe::fail(PFE_ECAPACITY, "more eigenvalues in the window than nev");
+  for (int i = 0; i < total; ++i) {
+    if (evals) evals[i] = kept[i].th;
+    if (resid) resid[i] = kept[i].res;
+  }
+  if (evecs && total > 0) {
+    const bool dev_out = (o.flags & PFE_DEVICE_PTRS) != 0;
+    PFE_HIP(hipMemcpyAsync(evecs, VB, (size_t)total * n * sizeof(double),
+                           dev_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+    PFE_TRY(sync(h));
+  }
+  agg.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st_out) *st_out = agg;
+  return pfe::ok();
+}
+
+pfe_status pfe_solve_sliced(pfe_handle h, double lam_lo, double lam_hi, int32_t nev,
+                            const pfe_solve_opts* opts, const pfe_slice_opts* slice_opts,
+                            int32_t* n_found, double* evals, double* evecs, double* resid,
+                            int32_t* n_slices, double* cuts, int32_t cuts_cap,
+                            pfe_solve_stats* stats) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, sliced_impl(h, lam_lo, lam_hi, nev, opts, slice_opts, n_found, evals, evecs,
+                               resid, n_slices, cuts, cuts_cap, stats));
 }
 
 // ---------------------------------------------------------------- adjoint

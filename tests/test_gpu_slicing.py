@@ -1,0 +1,122 @@
+"""GPU parity of spectrum slicing (end of Sec. 2.6; Sec. 6) and of the
+Chebyshev moments behind its cut placement (eq. eigval_count_estimator):
+sliced results against the plain definition (dense LAPACK), including cuts
+placed exactly on simple and on 24-fold degenerate eigenvalues."""
+import numpy as np
+import pytest
+
+import paper_1902_07041_amd as P
+from oracle import count, dense, filters as F, hessian, lanczos
+from synth import gaussian_block, gaussian_vector, lattice_glass
+
+from gpu_common import GlassCase, banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def case():
+    banner("glass N=1000 (slicing)")
+    c = GlassCase(1000)
+    c.h = c.handle()
+    _, c.ub, c.th = lanczos.lanczos_bounds(c.H, gaussian_vector(c.n, 7), 30)
+    P.pfe_set_bounds(c.h, 0.0, c.ub)
+    c.lo, c.hi = 0.01 * c.th, 0.03 * c.th
+    yield c
+    P.pfe_destroy(c.h)
+
+
+def check_window(H, lam, U, ub, lo, hi, out, ev_tol=1e-10):
+    want, V = dense.window(lam, U, lo, hi)
+    got = out["evals"]
+    assert got.shape == want.shape, (got, want)
+    assert np.max(np.abs(got - want) / np.abs(want)) <= ev_tol
+    Vg = out["evecs"].T
+    r = np.linalg.norm(H @ Vg - Vg * got[None, :], axis=0) / ub
+    assert r.max() <= 1e-9
+    # unit vectors; across slices (computed independently) two eigenvectors of
+    # eigenvalues a gap apart are orthogonal up to (r_a + r_b) lam_ub / gap; a
+    # duplicate would show an overlap near 1
+    G = Vg.T @ Vg
+    assert np.abs(np.diag(G) - 1).max() <= 1e-12
+    gap = np.abs(got[:, None] - got[None, :])
+    rr = out["resid"][:, None] + out["resid"][None, :]
+    off = ~np.eye(G.shape[0], dtype=bool)
+    bound = np.where(gap > 0, rr * ub / np.maximum(gap, 1e-300), np.inf)
+    assert np.all(np.abs(G[off]) <= np.minimum(bound[off], 1.0) + 1e-11)
+    assert np.abs(G[off]).max() < 1e-4
+    # same invariant subspace as the exact eigenvectors (principal angles of
+    # the spans, so the basis' own non-orthogonality does not enter)
+    Qg, _ = np.linalg.qr(Vg)
+    sv = np.linalg.svd(V.T @ Qg, compute_uv=False)
+    assert sv.min() > 1 - 1e-10
+
+
+def test_moments_parity(case):
+    banner("count moments K=200 M=16")
+    c, e = F.spectral_map(0.0, case.ub)
+    V = gaussian_block(case.n, 16, 13)
+    mu = P.pfe_count_moments(case.h, 200, 16, V)
+    ref = count.chebyshev_moments(case.H, c, e, V, 200)
+    np.testing.assert_allclose(mu, ref, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n_slices", [2, 3])
+def test_sliced_matches_dense(case, n_slices):
+    banner(f"sliced solve N=1000, {n_slices} slices (cuts from the count)")
+    out = P.pfe_solve_sliced(case.h, case.lo, case.hi, 40, 32, n_slices=n_slices, tol=1e-10)
+    assert out["n_slices"] == n_slices
+    assert out["cuts"][0] == case.lo and out["cuts"][-1] == case.hi
+    check_window(case.H, case.lam, case.U, case.ub, case.lo, case.hi, out)
+
+
+def test_sliced_auto_count(case):
+    banner("sliced solve, slice count from the estimate (4 per slice)")
+    out = P.pfe_solve_sliced(case.h, case.lo, case.hi, 40, 32, per_slice=4, tol=1e-10)
+    assert out["n_slices"] >= 2
+    check_window(case.H, case.lam, case.U, case.ub, case.lo, case.hi, out)
+
+
+def test_sliced_cuts_on_eigenvalues(case):
+    banner("sliced solve, cuts exactly on eigenvalues")
+    want, _ = dense.window(case.lam, case.U, case.lo, case.hi)
+    out = P.pfe_solve_sliced(case.h, case.lo, case.hi, 40, 32, cuts=[want[3], want[8]], tol=1e-10)
+    assert out["n_slices"] == 3
+    check_window(case.H, case.lam, case.U, case.ub, case.lo, case.hi, out)
+
+
+def test_sliced_splits_when_block_too_small(case):
+    banner("sliced solve, one slice over a block of 8: split on capacity")
+    out = P.pfe_solve_sliced(case.h, case.lo, case.hi, 40, 8, n_slices=1, tol=1e-10)
+    assert out["n_slices"] >= 2
+    check_window(case.H, case.lam, case.U, case.ub, case.lo, case.hi, out)
+
+
+def test_sliced_capacity(case):
+    banner("sliced solve, nev below the count")
+    with pytest.raises(P.PfeError) as e:
+        P.pfe_solve_sliced(case.h, case.lo, case.hi, 5, 32, n_slices=2, tol=1e-10)
+    assert e.value.status == -6
+
+
+def test_sliced_degenerate_cluster_on_cut():
+    """Perfect simple-cubic lattice (no jitter, equal masses and springs):
+    eigenvalues 1/12 and 1/6 of lambda_max with multiplicities 12 and 24; a cut
+    exactly on the 24-fold one must return it once, as a full eigenspace."""
+    banner("sliced solve, perfect lattice N=216, cut on a 24-fold eigenvalue")
+    g = lattice_glass(216, seed=1, jitter=0.0, mass_b=63.5, k_lo=1.0, k_hi=1.0)
+    H, hb = hessian.glass_H(g)
+    lam, U = np.linalg.eigh(H.toarray())
+    ub = 1.02 * lam[-1]
+    lo, hi = 0.05 * lam[-1], 0.19 * lam[-1]
+    want, V = dense.window(lam, U, lo, hi)
+    assert want.size == 36
+    h = P.pfe_create(0)
+    try:
+        P.pfe_set_hessian(h, g.row_ptr, g.col_idx, g.blocks, g.masses)
+        P.pfe_set_bounds(h, 0.0, ub)
+        out = P.pfe_solve_sliced(h, lo, hi, 60, 48, cuts=[want[20]], tol=1e-10)
+        assert out["n_slices"] == 2
+        check_window(H, lam, U, ub, lo, hi, out)
+    finally:
+        P.pfe_destroy(h)

@@ -102,6 +102,12 @@ def test_solve_seeded_start_and_capacity(case):
     with pytest.raises(P.PfeError) as e:
         P.pfe_solve_interval(case.h, case.lo, case.hi, 5, 32, degree=80, tol=1e-10, seed=3)
     assert e.value.status == -6
+    # a block of 8 for 12 eigenvalues: every Ritz value ends in the window,
+    # which the solver reports instead of returning a subset
+    with pytest.raises(P.PfeError) as e:
+        P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 8, degree=80, tol=1e-10, seed=3,
+                             max_iter=60)
+    assert e.value.status in (-6, -5)
 
 
 def test_solve_bounds_too_small_is_detected(case):

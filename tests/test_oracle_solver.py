@@ -153,3 +153,33 @@ def test_count_estimator(g1000):
     coef = count.chi_coefficients((lo - c) / e, (hi - c) / e, 300)
     tr = np.sum(F.cheb_eval(coef, np.clip((lam - c) / e, -1, 1)))
     assert abs(tr - exact) < 2.0
+
+
+def test_chebyshev_moments_closed_form_and_trace():
+    """Moments against the eigen-expansion sum_i (u_i.v)^2 cos(k acos lam_i);
+    with the unit basis as probes (M = n) the count from the moments is the
+    exact trace of the damped series, and any window count equals the
+    direct estimator on the same probes."""
+    g = lattice_glass(125, seed=3)
+    H, _ = hessian.glass_H(g)
+    Hd = H.toarray()
+    lam, U = np.linalg.eigh(Hd)
+    n = Hd.shape[0]
+    ub = lam[-1] * 1.02
+    c, e = F.spectral_map(0.0, ub)
+    V = gaussian_block(n, 7, 5)
+    K = 60
+    mu = count.chebyshev_moments(H, c, e, V, K)
+    Vn = V / np.linalg.norm(V, axis=0)
+    w = np.mean((U.T @ Vn) ** 2, axis=1)                      # spectral weights
+    x = np.clip((lam - c) / e, -1.0, 1.0)        # zero modes sit at -1 up to rounding
+    th = np.arccos(x)
+    ref = np.array([np.sum(w * np.cos(k * th)) for k in range(K + 1)])
+    np.testing.assert_allclose(mu, ref, rtol=0, atol=1e-12)
+    xi, eta = (0.1 * lam[-1] - c) / e, (0.4 * lam[-1] - c) / e
+    est = count.count_from_moments(mu, n, xi, eta)
+    direct = count.count_estimate(H, c, e, xi, eta, V, k=K)
+    assert est == pytest.approx(direct, rel=1e-12)
+    mu_all = count.chebyshev_moments(H, c, e, np.eye(n), K)
+    tr = np.sum(F.cheb_eval(count.chi_coefficients(xi, eta, K), x))
+    assert count.count_from_moments(mu_all, n, xi, eta) == pytest.approx(tr, rel=1e-11)

@@ -1,0 +1,146 @@
+"""GPU parity at the benchmark's full size: the 100 000-atom glass
+(n = 300 000, 1.7 M stored blocks), block 96, in the launch configuration the
+benchmark times.
+
+* Lanczos bounds and the FP64 / FP32 filter against the oracle on every row
+  (the oracle's BSR product runs in plain C so this takes seconds);
+* the FP64 solve and the FP32-filter form against the window's eigenvalues
+  stored in golden/glass100k_window.json, which the CPU oracle alone wrote
+  (golden/make_glass100k_window.py), plus residuals and orthonormality
+  recomputed on the CPU;
+* the filter adjoint against the oracle at a small degree, and the
+  self-adjointness of p(H_hat) at the benchmark's degree 150;
+* the Hellmann-Feynman gradient and the spring chain rule of found
+  eigenvectors against the oracle.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_1902_07041_amd as P
+from oracle import adjoint, cbsr, chebyshev, filters as F, hessian, lanczos
+from synth import gaussian_block, gaussian_vector, lattice_glass
+
+from gpu_common import banner, rel_err
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN_PATH = os.path.join(os.path.dirname(__file__), "golden", "glass100k_window.json")
+GOLDEN = json.load(open(GOLDEN_PATH)) if os.path.exists(GOLDEN_PATH) else None
+
+
+class Full:
+    pass
+
+
+@pytest.fixture(scope="module")
+def full():
+    assert GOLDEN is not None, f"missing {GOLDEN_PATH} (written by make_glass100k_window.py)"
+    banner("glass N=100000 (full size)")
+    s = Full()
+    s.g = lattice_glass(GOLDEN["n_atoms"], seed=GOLDEN["seed"])
+    s.n = s.g.n
+    s.hb = hessian.weight_blocks(s.g.row_ptr, s.g.col_idx, s.g.blocks, s.g.masses)
+    s.H = cbsr.BsrOperator(s.g.row_ptr, s.g.col_idx, s.hb)
+    s.h = P.pfe_create(0)
+    P.pfe_set_hessian(s.h, s.g.row_ptr, s.g.col_idx, s.g.blocks, s.g.masses)
+    v0 = gaussian_vector(s.n, GOLDEN["v0_seed"])
+    s.lb, s.ub, s.th = P.pfe_estimate_bounds(s.h, GOLDEN["lanczos_steps"], v0)
+    s.lo, s.hi = GOLDEN["win"][0] * s.th, GOLDEN["win"][1] * s.th
+    s.X0 = gaussian_block(s.n, GOLDEN["block"], GOLDEN["x0_seed"])
+    yield s
+    P.pfe_destroy(s.h)
+
+
+def test_full_bounds(full):
+    banner("full bounds vs oracle Lanczos")
+    _, rub, rth = lanczos.lanczos_bounds(full.H, gaussian_vector(full.n, GOLDEN["v0_seed"]),
+                                         GOLDEN["lanczos_steps"])
+    assert full.lb == 0.0
+    assert abs(full.th - rth) <= 1e-12 * rth
+    assert abs(full.ub - rub) <= 1e-10 * rub
+    assert abs(full.th - GOLDEN["theta_max"]) <= 1e-12 * rth
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_filter(full, prec):
+    banner(f"full filter {prec} q=96 d=5")
+    f = P.pfe_design_filter(full.lo, full.hi, full.lb, full.ub, degree=5)
+    ref = chebyshev.apply_filter(full.H, f.c, f.e, f.coef, full.X0)
+    if prec == "fp64":
+        Y = P.pfe_apply_filter(full.h, f, full.X0)
+        assert rel_err(Y, ref) <= 1e-12
+    else:
+        Y = P.pfe_apply_filter(full.h, f, full.X0.astype(np.float32))
+        # FP32 rounding of H_hat and of every step; the same bound as the
+        # degree-30 small case, which the CPU measured for this growth
+        assert rel_err(Y, ref) <= 5e-5
+
+
+def _check_solve(full, out, ev_tol, res_tol):
+    want = np.asarray(GOLDEN["evals"])
+    assert out["status"] == "PFE_OK", out["stats"]
+    assert out["evals"].shape == want.shape
+    assert np.max(np.abs(out["evals"] - want) / want) <= ev_tol
+    V = np.ascontiguousarray(out["evecs"].T)            # n x m
+    R = full.H @ V - V * out["evals"][None, :]
+    res = np.linalg.norm(R, axis=0) / full.ub
+    assert res.max() <= res_tol
+    assert np.abs(V.T @ V - np.eye(V.shape[1])).max() <= 1e-10
+    return V
+
+
+def test_full_solve_fp64(full):
+    banner("full solve fp64 q=96 d=400 (benchmark configuration)")
+    out = P.pfe_solve_interval(full.h, full.lo, full.hi, 96, GOLDEN["block"], degree=GOLDEN["degree"],
+                               tol=1e-10, x0=full.X0)
+    full.V = _check_solve(full, out, 1e-10, 1e-10)
+    full.lam = out["evals"]
+
+
+def test_full_solve_fp32_form(full):
+    banner("full solve fp32-filter form q=96 d=400 (benchmark configuration)")
+    out = P.pfe_solve_interval(full.h, full.lo, full.hi, 96, GOLDEN["block"], degree=GOLDEN["degree"],
+                               tol=1e-8, precision=P.PFE_FP32, x0=full.X0)
+    _check_solve(full, out, 1e-8, 1e-8)
+    assert out["stats"]["refined"] == 1
+
+
+def test_full_adjoint_small_degree(full):
+    banner("full adjoint q=64 d=4 stride 2 vs oracle")
+    f = P.pfe_design_filter(full.lo, full.hi, full.lb, full.ub, degree=4)
+    X = gaussian_block(full.n, 64, 21)
+    W = gaussian_block(full.n, 64, 22)
+    dX, dB = P.pfe_apply_filter_adjoint(full.h, f, X, W, full.g.nnzb, 2)
+    rX, rG = adjoint.filter_vjp_blocks(full.H, full.g.row_ptr, full.g.col_idx, f.c, f.e, f.coef, X, W)
+    assert rel_err(dX, rX) <= 1e-12
+    assert rel_err(dB, rG) <= 1e-11
+
+
+def test_full_adjoint_self_adjoint_d150(full):
+    banner("full adjoint q=64 d=150: dX = p(H_hat) dY")
+    f = P.pfe_design_filter(full.lo, full.hi, full.lb, full.ub, degree=150)
+    X = gaussian_block(full.n, 64, 21)
+    W = gaussian_block(full.n, 64, 22)
+    dX, _ = P.pfe_apply_filter_adjoint(full.h, f, X, W, full.g.nnzb, 0)
+    # p(H_hat) is symmetric, so the input gradient is the filter applied to dY
+    assert rel_err(dX, P.pfe_apply_filter(full.h, f, W)) <= 1e-12
+
+
+def test_full_hellmann_feynman(full):
+    banner("full Hellmann-Feynman gradient + chain rule")
+    if not hasattr(full, "V"):
+        pytest.skip("needs the FP64 solve's eigenvectors")
+    g = full.g
+    V = np.ascontiguousarray(full.V[:, :8].T)
+    w = np.linspace(1.0, 2.0, 8)
+    dB = P.pfe_eigvec_block_gradient(full.h, V, g.nnzb, w)
+    ref = sum(wi * adjoint.hellmann_feynman_blocks(V[s], g.row_ptr, g.col_idx) for s, wi in enumerate(w))
+    assert rel_err(dB, ref) <= 1e-13
+    dk, dm = P.pfe_spring_gradient(full.h, g.pairs, g.unit, dB, g.n_atoms)
+    rk, rm = adjoint.spring_chain_rule(ref, full.hb, g.row_ptr, g.col_idx, g.pairs, g.unit, g.masses)
+    assert rel_err(dk, rk) <= 1e-12
+    assert rel_err(dm, rm) <= 1e-12
+    assert np.sum(g.k * dk) == pytest.approx(np.sum(w * full.lam[:8]), rel=1e-10)

@@ -222,10 +222,12 @@ typedef struct {
   double t_orth;             /* CholQR2 */
   double t_rr;               /* Rayleigh-Ritz incl. H X and the small eigensolve */
   double t_resid;            /* residuals and selection */
-  double gemm_flops;         /* Gram + projection flops */
+  double gemm_flops;         /* flops of the MFMA kernels (Gram and tall GEMM, 2 n q^2
+                                each) in CholQR2 and Rayleigh-Ritz */
   double max_resid;          /* largest returned residual */
   int32_t n_window;          /* in-window Ritz values at the end */
   int64_t filter_columns;    /* sum over iterations of the filtered columns */
+  double t_gemm;             /* seconds in those MFMA kernels (events on the stream) */
 } pfe_solve_stats;
 
 /* Fill opts with defaults (block 0 must then be set by the caller). */

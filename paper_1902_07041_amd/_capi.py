@@ -56,7 +56,7 @@ class CSolveStats(C.Structure):
                 ("filter_bytes", C.c_double), ("t_total", C.c_double), ("t_filter", C.c_double),
                 ("t_orth", C.c_double), ("t_rr", C.c_double), ("t_resid", C.c_double),
                 ("gemm_flops", C.c_double), ("max_resid", C.c_double), ("n_window", C.c_int32),
-                ("filter_columns", C.c_int64)]
+                ("filter_columns", C.c_int64), ("t_gemm", C.c_double)]
 
 
 _lib = None

@@ -43,7 +43,7 @@ struct pfe_ctx {
   DevBuf wsOut;                 // eigenvector output staging
   DevBuf wsCk;                  // adjoint checkpoints
   DevBuf wsSlice;               // eigenvectors collected over the slices of a sliced solve
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // [0,1] phase timers, [2,3] MFMA kernels
 
   pfe::Bsr bsr() const {
     pfe::Bsr a;
@@ -123,7 +123,9 @@ struct Timer {
   hipStream_t s;
   double* acc;
   bool on;
-  Timer(pfe_handle h, double* acc_) : a(h->ev[0]), b(h->ev[1]), s(h->stream), acc(acc_), on(acc_ != nullptr) {
+  // pair 0: phase timers; pair 1: the MFMA kernels inside a phase
+  Timer(pfe_handle h, double* acc_, int pair = 0)
+      : a(h->ev[2 * pair]), b(h->ev[2 * pair + 1]), s(h->stream), acc(acc_), on(acc_ != nullptr) {
     if (on) (void)hipEventRecord(a, s);
   }
   void stop() {
@@ -270,12 +272,24 @@ Err ensure_red(pfe_handle h, int64_t n, int q) {
 // shifted CholeskyQR of Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa)
 // is inserted and followed by the two plain passes.  On the first pass the
 // largest squared column norm is compared with `norm_bound`^2 (EBOUNDS).
+// Time and flops of the MFMA kernels (Gram and tall GEMM), 2 n q^2 each.
+struct GemmAcct {
+  double t = 0, flops = 0;
+  bool on = false;
+};
+
 Err cholqr2(pfe_handle h, const Small& sm, double* X, int64_t n, int q, int64_t ld,
-            double norm_bound) {
+            double norm_bound, GemmAcct* ga = nullptr) {
+  const bool tg = ga && ga->on;
+  const double f2 = 2.0 * (double)n * q * q;
   int passes = 2;
   bool shifted_done = false;
   for (int pass = 0; pass < passes; ++pass) {
-    PFE_HIP(pfe::gram_f64(n, q, q, X, ld, X, ld, sm.G, h->wsRed.p, h->stream));
+    {
+      Timer tm(h, tg ? &ga->t : nullptr, 1);
+      PFE_HIP(pfe::gram_f64(n, q, q, X, ld, X, ld, sm.G, h->wsRed.p, h->stream));
+    }
+    if (ga) ga->flops += f2;
     PFE_HIP(pfe::chol_inv_f64(q, sm.G, 0.0, sm.Rinv, sm.info, sm.dmax, h->stream));
     int info = 0;
     double dmax = 0;
@@ -299,7 +313,11 @@ Err cholqr2(pfe_handle h, const Small& sm, double* X, int64_t n, int q, int64_t 
       shifted_done = true;
       passes += 1;
     }
-    PFE_HIP(pfe::gemm_tall_f64(n, q, q, X, ld, sm.Rinv, X, ld, h->stream));
+    {
+      Timer tm(h, tg ? &ga->t : nullptr, 1);
+      PFE_HIP(pfe::gemm_tall_f64(n, q, q, X, ld, sm.Rinv, X, ld, h->stream));
+    }
+    if (ga) ga->flops += f2;
   }
   return pfe::ok();
 }
@@ -308,16 +326,25 @@ Err cholqr2(pfe_handle h, const Small& sm, double* X, int64_t n, int q, int64_t 
 // residuals ||W_j - theta_j X_j|| / lam_ub.  Theta and residuals to host.
 Err rayleigh_ritz(pfe_handle h, const Small& sm, double* X, double* W, int64_t n, int q,
                   int64_t ld, std::vector<double>& theta, std::vector<double>& res,
-                  double* t_rr, double* t_res) {
+                  double* t_rr, double* t_res, GemmAcct* ga = nullptr) {
   const pfe::Bsr A = h->bsr();
+  const bool tg = ga && ga->on;
+  const double f2 = 2.0 * (double)n * q * q;
   {
     Timer tm(h, t_rr);
     PFE_HIP(pfe::cheb_step_f64(A, h->step_vals64(), X, nullptr, nullptr, W, q, ld, 1.0, 0.0,
                                0.0, 0.0, h->stream));
-    PFE_HIP(pfe::gram_f64(n, q, q, X, ld, W, ld, sm.S, h->wsRed.p, h->stream));
+    {
+      Timer tg1(h, tg ? &ga->t : nullptr, 1);
+      PFE_HIP(pfe::gram_f64(n, q, q, X, ld, W, ld, sm.S, h->wsRed.p, h->stream));
+    }
     PFE_HIP(pfe::sym_eig_f64(q, sm.S, sm.theta, sm.Q, sm.jw, sm.info, h->stream));
-    PFE_HIP(pfe::gemm_tall_f64(n, q, q, X, ld, sm.Q, X, ld, h->stream));
-    PFE_HIP(pfe::gemm_tall_f64(n, q, q, W, ld, sm.Q, W, ld, h->stream));
+    {
+      Timer tg2(h, tg ? &ga->t : nullptr, 1);
+      PFE_HIP(pfe::gemm_tall_f64(n, q, q, X, ld, sm.Q, X, ld, h->stream));
+      PFE_HIP(pfe::gemm_tall_f64(n, q, q, W, ld, sm.Q, W, ld, h->stream));
+    }
+    if (ga) ga->flops += 3.0 * f2;
   }
   {
     Timer tm(h, t_res);
@@ -384,7 +411,8 @@ pfe_status pfe_create(int device, void* hip_stream, pfe_handle* out) {
       return create_fail(h, PFE_EHIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
     h->own_stream = true;
   }
-  if ((e = hipEventCreate(&h->ev[0])) != hipSuccess || (e = hipEventCreate(&h->ev[1])) != hipSuccess)
+  if ((e = hipEventCreate(&h->ev[0])) != hipSuccess || (e = hipEventCreate(&h->ev[1])) != hipSuccess ||
+      (e = hipEventCreate(&h->ev[2])) != hipSuccess || (e = hipEventCreate(&h->ev[3])) != hipSuccess)
     return create_fail(h, PFE_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
   if ((e = h->flags.ensure(256)) != hipSuccess)
     return create_fail(h, PFE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -862,6 +890,8 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   double prev_max = HUGE_VAL;
   const pfe::Bsr A = h->bsr();
   std::vector<int> perm(q);
+  GemmAcct ga;
+  ga.on = true;
   for (int it = 1; it <= o.max_iter; ++it) {
     // Locking: the Ritz vectors of the last Rayleigh-Ritz step that lie in the
     // window with residual <= tol are not filtered.  The others (rounded up
@@ -919,7 +949,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     }
     {
       Timer tm(h, &st.t_orth);
-      PFE_TRY(cholqr2(h, sm, Fout, n, q, ld, bound));
+      PFE_TRY(cholqr2(h, sm, Fout, n, q, ld, bound, &ga));
     }
     if (Fout == W) {
       std::swap(h->wsA.p, h->wsB.p);
@@ -927,7 +957,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       X = h->wsA.as<double>();
       W = h->wsB.as<double>();
     }
-    PFE_TRY(rayleigh_ritz(h, sm, X, W, n, q, ld, theta, res, &st.t_rr, &st.t_resid));
+    PFE_TRY(rayleigh_ritz(h, sm, X, W, n, q, ld, theta, res, &st.t_rr, &st.t_resid, &ga));
     st.iterations = it;
     int cnt = 0;
     bool ok_all = true;
@@ -961,7 +991,8 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     prev_cnt = cnt;
     prev_max = mx;
   }
-  st.gemm_flops = 0;
+  st.gemm_flops = ga.flops;
+  st.t_gemm = ga.t;
   // in-window selection (ascending theta)
   std::vector<int> sel;
   for (int j = 0; j < q; ++j)
@@ -1283,6 +1314,8 @@ static Err sliced_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     agg.t_orth += ss.t_orth;
     agg.t_rr += ss.t_rr;
     agg.t_resid += ss.t_resid;
+    agg.t_gemm += ss.t_gemm;
+    agg.gemm_flops += ss.gemm_flops;
     agg.c = ss.c;
     agg.e = ss.e;
     if (r.st == PFE_ECAPACITY || r.st == PFE_ENOCONV) {

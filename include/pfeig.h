@@ -251,6 +251,63 @@ pfe_status pfe_solve_interval(pfe_handle h, double lam_lo, double lam_hi, int32_
                               const pfe_solve_opts* opts, int32_t* n_found, double* evals,
                               double* evecs, double* resid, pfe_solve_stats* stats);
 
+/* ------------------------------------------------ Dirac filter + Lanczos */
+typedef struct {
+  int32_t degree;      /* k */
+  int32_t smoothing;
+  double c, e;         /* H_hat = (H - c I)/e */
+  double xi, eta;      /* mapped window */
+  double gamma;        /* centre, balanced so that rho(xi) = rho(eta) */
+  double tau;          /* rho(xi) = rho(eta): eigenvalues of rho(H_hat) above it are wanted */
+  double peak;         /* rho(gamma) */
+  const double* coef;  /* k+1 coefficients g_j T_j(gamma) / <T_j, T_j>; caller-owned */
+} pfe_dirac_filter;
+
+/* Host-only, pure: the Dirac-delta filter of Sec. 2.5 (eq. cheby-delta.1,
+ * damping of Sec. 2.3) for [lam_lo, lam_hi] within [lam_lb, lam_ub].
+ * degree 0: the smallest k with rho_k(xi) / rho_k(gamma) <= phi (the reading
+ * that reproduces the Dirac degrees of Tables 1-3); gamma by bisection so that
+ * rho_k(xi) = rho_k(eta).  Writes k+1 coefficients to coef_out (ECAPACITY, with
+ * out->degree set, if coef_cap is smaller). */
+pfe_status pfe_design_dirac(double lam_lo, double lam_hi, double lam_lb, double lam_ub,
+                            int32_t degree, double phi, int32_t smoothing, double* coef_out,
+                            int32_t coef_cap, pfe_dirac_filter* out);
+
+typedef struct {
+  int32_t block;         /* Lanczos block size b (1..64; default 16) */
+  int32_t max_basis;     /* basis size m before a restart (multiple of b, 3b <= m,
+                            m + b <= 511; 0: max(4b, 3 nev), the paper's 3 nev) */
+  int32_t degree;        /* Dirac filter degree (0: by phi) */
+  double phi;            /* rho(xi) / rho(gamma) target (0 -> 0.8, as chosen in Sec. 4.1) */
+  int32_t smoothing;     /* PFE_SMOOTH_* */
+  double tol;            /* residual ||H v - lambda v|| / lam_ub (0 -> 1e-10) */
+  int32_t max_restarts;  /* restart cycles (0 -> 200) */
+  uint64_t seed;         /* start block seed */
+  uint32_t flags;        /* PFE_DEVICE_PTRS applies to evecs */
+} pfe_lanczos_opts;
+
+void pfe_lanczos_opts_default(pfe_lanczos_opts* opts);
+
+/* Eigenpairs of H in [lam_lo, lam_hi] by block Lanczos with thick restart on
+ * rho_k(H_hat) (Sec. 2.5 and Sec. 3, the Krylov alternative to subspace
+ * iteration): every new block is projected against the basis twice
+ * (classical Gram-Schmidt) and orthonormalised by CholQR2 (a block without
+ * new directions is refilled with random ones), T = V^T rho(H_hat) V is
+ * formed from Gram products, and a thick restart keeps the largest
+ * Ritz vectors.  When every Ritz value >= tau has a rho-residual below
+ * 0.1 tol rho(gamma) in two consecutive cycles with the same count, one
+ * Rayleigh-Ritz step on H over those Ritz vectors gives the eigenpairs; if an
+ * H residual near the window is still above tol the rho-tolerance is lowered
+ * 100-fold and the iteration continues (at most four times).  Outputs as
+ * pfe_solve_interval; stats->iterations counts restart cycles.  ECAPACITY if
+ * more than m - 2b Ritz values exceed tau or the window holds more than nev.
+ * A block Krylov space holds at most b directions of one eigenspace: an
+ * eigenvalue of multiplicity above b is returned at most b times (subspace
+ * iteration, pfe_solve_interval, has no such limit below its block size). */
+pfe_status pfe_solve_lanczos(pfe_handle h, double lam_lo, double lam_hi, int32_t nev,
+                             const pfe_lanczos_opts* opts, int32_t* n_found, double* evals,
+                             double* evecs, double* resid, pfe_solve_stats* stats);
+
 /* Spectrum slicing (end of Sec. 2.6; Sec. 6): eigenpairs in [lam_lo, lam_hi]
  * when they do not fit one subspace.  The window is cut into sub-windows
  * (explicit cuts, or where the count estimate of eq. eigval_count_estimator

@@ -43,6 +43,18 @@ class CSolveOpts(C.Structure):
                 ("x0", C.c_void_p), ("flags", C.c_uint32), ("locking", C.c_int32)]
 
 
+class CDiracFilter(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("smoothing", C.c_int32), ("c", C.c_double), ("e", C.c_double),
+                ("xi", C.c_double), ("eta", C.c_double), ("gamma", C.c_double), ("tau", C.c_double),
+                ("peak", C.c_double), ("coef", C.c_void_p)]
+
+
+class CLanczosOpts(C.Structure):
+    _fields_ = [("block", C.c_int32), ("max_basis", C.c_int32), ("degree", C.c_int32),
+                ("phi", C.c_double), ("smoothing", C.c_int32), ("tol", C.c_double),
+                ("max_restarts", C.c_int32), ("seed", C.c_uint64), ("flags", C.c_uint32)]
+
+
 class CSliceOpts(C.Structure):
     _fields_ = [("n_slices", C.c_int32), ("per_slice", C.c_int32), ("margin", C.c_double),
                 ("count_degree", C.c_int32), ("count_samples", C.c_int32), ("count_seed", C.c_uint64),
@@ -114,10 +126,16 @@ def load_library():
                                    C.POINTER(i32), vp, vp, vp, C.POINTER(i32), vp, i32,
                                    C.POINTER(CSolveStats)]
     L.pfe_count_moments.argtypes = [vp, i32, i32, vp, u64, u32, vp]
+    L.pfe_design_dirac.argtypes = [dbl, dbl, dbl, dbl, i32, dbl, i32, vp, i32, C.POINTER(CDiracFilter)]
+    L.pfe_lanczos_opts_default.argtypes = [C.POINTER(CLanczosOpts)]
+    L.pfe_lanczos_opts_default.restype = None
+    L.pfe_solve_lanczos.argtypes = [vp, dbl, dbl, i32, C.POINTER(CLanczosOpts), C.POINTER(i32), vp,
+                                    vp, vp, C.POINTER(CSolveStats)]
     for name in ("pfe_create", "pfe_set_hessian", "pfe_set_springs", "pfe_estimate_bounds", "pfe_set_bounds",
                  "pfe_design_filter", "pfe_apply_filter", "pfe_apply_filter_adjoint",
                  "pfe_eigvec_block_gradient", "pfe_spring_gradient", "pfe_solve_interval",
-                 "pfe_estimate_count", "pfe_solve_sliced", "pfe_count_moments"):
+                 "pfe_estimate_count", "pfe_solve_sliced", "pfe_count_moments", "pfe_design_dirac",
+                 "pfe_solve_lanczos"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -442,6 +460,75 @@ def pfe_solve_sliced(h, lam_lo, lam_hi, nev, block, n_slices=0, per_slice=0, mar
     return {"evals": ev[:k].copy(), "evecs": None if vecs is None else vecs[:k],
             "resid": rs[:k].copy(), "stats": sd, "status": STATUS.get(st, st),
             "n_slices": ns.value, "cuts": cut_out[: ns.value + 1].copy()}
+
+
+@dataclass
+class DiracFilter:
+    degree: int
+    smoothing: int
+    c: float
+    e: float
+    xi: float
+    eta: float
+    gamma: float
+    tau: float
+    peak: float
+    coef: np.ndarray
+
+
+def pfe_design_dirac(lam_lo, lam_hi, lam_lb, lam_ub, degree=0, phi=0.8,
+                     smoothing=PFE_SMOOTH_NONE) -> DiracFilter:
+    """Dirac-delta filter (host only)."""
+    L = load_library()
+    out = CDiracFilter()
+    cap = max(degree + 1, 1)
+    while True:
+        buf = np.zeros(cap)
+        st = L.pfe_design_dirac(lam_lo, lam_hi, lam_lb, lam_ub, degree, phi, smoothing,
+                                buf.ctypes.data, cap, C.byref(out))
+        if st == -6 and out.degree + 1 > cap:
+            cap = out.degree + 1
+            degree = out.degree      # keep the degree found, skip the search
+            continue
+        if st != 0:
+            raise PfeError(st, "pfe_design_dirac failed")
+        return DiracFilter(out.degree, out.smoothing, out.c, out.e, out.xi, out.eta, out.gamma,
+                           out.tau, out.peak, buf[: out.degree + 1].copy())
+
+
+def pfe_solve_lanczos(h, lam_lo, lam_hi, nev, block=16, max_basis=0, degree=0, phi=0.8,
+                      smoothing=PFE_SMOOTH_NONE, tol=0.0, max_restarts=0, seed=11,
+                      want_vectors=True, vectors_on_device=False):
+    """Eigenpairs in [lam_lo, lam_hi] by thick-restart block Lanczos on the
+    Dirac filter.  Returns a dict like pfe_solve_interval."""
+    L = load_library()
+    o = CLanczosOpts()
+    L.pfe_lanczos_opts_default(C.byref(o))
+    o.block, o.max_basis, o.degree, o.phi, o.smoothing = block, max_basis, degree, phi, smoothing
+    o.tol, o.max_restarts, o.seed = tol, max_restarts, seed
+    o.flags = PFE_DEVICE_PTRS if vectors_on_device else 0
+    n_found = C.c_int32()
+    ev = np.zeros(max(nev, 1))
+    rs = np.zeros(max(nev, 1))
+    stats = CSolveStats()
+    vecs = None
+    p_vec = None
+    if want_vectors and nev > 0 and h.value in _N:
+        n = _n_of(h)
+        if vectors_on_device:
+            import torch
+            vecs = torch.zeros((nev, n), dtype=torch.float64, device="cuda")
+            p_vec = vecs.data_ptr()
+        else:
+            vecs = np.zeros((nev, n))
+            p_vec = vecs.ctypes.data
+    st = L.pfe_solve_lanczos(h, lam_lo, lam_hi, nev, C.byref(o), C.byref(n_found), ev.ctypes.data,
+                             p_vec, rs.ctypes.data, C.byref(stats))
+    _check(h, st)
+    k = n_found.value
+    sd = {f: getattr(stats, f) for f, _ in CSolveStats._fields_}
+    return {"evals": ev[:k].copy(), "evecs": None if vecs is None else vecs[:k],
+            "resid": rs[:k].copy(), "stats": sd, "status": STATUS.get(st, st)}
 
 
 def pfe_count_moments(h, K: int, nsamples: int = 32, V=None, seed: int = 13):

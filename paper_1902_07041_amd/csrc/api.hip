@@ -1444,6 +1444,317 @@ pfe_status pfe_solve_sliced(pfe_handle h, double lam_lo, double lam_hi, int32_t 
                                resid, n_slices, cuts, cuts_cap, stats));
 }
 
+// ------------------------------------------------------ thick-restart Lanczos
+// Eigenpairs in [lam_lo, lam_hi] by block Lanczos with thick restart on the
+// Dirac-delta filter rho_k(H_hat) (Sec. 2.5 and Sec. 3): the eigenvectors of
+// rho_k(H_hat) with eigenvalue >= tau = rho_k(xi) = rho_k(eta) span the wanted
+// eigenvectors of H, which a Rayleigh-Ritz step on H extracts.
+//
+// Basis V [n][ldv] of up to m + b columns.  Each expansion step filters the
+// last block into the next b columns, keeps a copy, projects the new block
+// against the basis twice and orthonormalises it (full re-orthogonalisation),
+// and takes the new block column of T = V^T rho(H_hat) V from one Gram
+// product with the kept copy, so T is computed, not assumed tridiagonal.  With m columns the Ritz pairs of T_m
+// give residuals ||B s_last||; a thick restart keeps the k largest Ritz
+// vectors (X <- V S_k), moves the residual block after them and restarts T as
+// diag(theta) with the arrow coupling B S_last,k.
+static Err lanczos_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
+                        const pfe_lanczos_opts* o_in, int* n_found, double* evals, double* evecs,
+                        double* resid, pfe_solve_stats* st_out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  PFE_TRY(select_device(h));
+  if (!h->has_h) return pfe::fail(PFE_ESTATE, "no Hessian set");
+  if (!h->has_bounds) return pfe::fail(PFE_ESTATE, "no spectral bounds (estimate_bounds or set_bounds)");
+  pfe_lanczos_opts o;
+  pfe_lanczos_opts_default(&o);
+  if (o_in) o = *o_in;
+  const int64_t n = h->n();
+  const int b = o.block;
+  if (b < 1 || b > 64) return pfe::fail(PFE_EINVAL, "block must be in [1, 64]");
+  if (nev < 0 || !n_found) return pfe::fail(PFE_EINVAL, "nev >= 0 and n_found required");
+  int m = o.max_basis > 0 ? o.max_basis : (int)std::max<int64_t>(4 * b, 3 * (int64_t)std::max(nev, 1));
+  m = (int)round_up(m, b);
+  if (m + b > 511 || m < 3 * b) return pfe::fail(PFE_EINVAL, "max_basis must give 3 block <= m and m + block <= 511");
+  if (m + b > n) return pfe::fail(PFE_EINVAL, "basis larger than the matrix");
+  if (lam_lo < h->lam_lb || lam_hi > h->lam_ub)
+    return pfe::fail(PFE_EINVAL, "window must lie inside [lam_lb, lam_ub]");
+  const double tol = o.tol > 0 ? o.tol : 1e-10;
+  const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 200;
+  pfe::DiracDesign dd;
+  PFE_TRY(pfe::design_dirac(lam_lo, lam_hi, h->lam_lb, h->lam_ub, o.degree, o.phi > 0 ? o.phi : 0.8,
+                            o.smoothing, &dd));
+  pfe_solve_stats st;
+  std::memset(&st, 0, sizeof(st));
+  st.degree = dd.degree;
+  st.c = dd.c;
+  st.e = dd.e;
+  st.xi = dd.xi;
+  st.eta = dd.eta;
+  const int64_t ldv = round_up(m + b, 8);
+  const size_t mvb = (size_t)n * ldv * sizeof(double);
+  PFE_HIP(h->wsA.ensure(mvb));                                   // V
+  PFE_HIP(h->wsB.ensure(mvb));                                   // filter scratch / Ritz vectors
+  PFE_HIP(h->wsC.ensure(mvb));                                   // H X in the extraction
+  PFE_HIP(h->wsD.ensure((size_t)n * round_up(b, 8) * sizeof(double)));   // kept rho(H) V_j
+  double* V = h->wsA.as<double>();
+  double* Scr = h->wsB.as<double>();
+  double* Wx = h->wsC.as<double>();
+  double* Wk = h->wsD.as<double>();
+  const int64_t ldk = round_up(b, 8);
+  PFE_HIP(pfe::zero_f64(V, n * ldv, h->stream));
+  PFE_HIP(pfe::zero_f64(Scr, n * ldv, h->stream));
+  PFE_HIP(pfe::zero_f64(Wk, n * ldk, h->stream));
+  Small sm;
+  PFE_TRY(alloc_small(h, m + b, &sm));
+  PFE_TRY(ensure_red(h, n, m + b));
+  // Orthonormalise block B (b columns at ld ldv) against V[:, 0:p] (two
+  // projection passes, classical Gram-Schmidt) and in itself (CholQR2).  A
+  // block that has (numerically) no part outside span(V) is replaced by
+  // random directions, projected the same way: the Krylov space has then
+  // closed over those directions, and T stays exact because it is formed
+  // from the kept filtered block.
+  int refills = 0;
+  auto project = [&](double* B, int p0) -> Err {
+    for (int pass = 0; pass < 2 && p0 > 0; ++pass) {
+      PFE_HIP(pfe::gram_f64(n, p0, b, V, ldv, B, ldv, sm.G, h->wsRed.p, h->stream));
+      PFE_HIP(pfe::gemm_tall_f64(n, p0, b, V, ldv, sm.G, Scr, ldv, h->stream));
+      PFE_HIP(pfe::sub_cols_f64(n, b, Scr, ldv, B, ldv, h->stream));
+    }
+    return pfe::ok();
+  };
+  auto orth_block = [&](double* Vb, int p0, double* B) -> Err {
+    (void)Vb;
+    PFE_TRY(project(B, p0));
+    Err e = cholqr2(h, sm, B, n, b, ldv, -1.0);
+    for (int tries = 0; e.st == PFE_EBREAKDOWN && tries < 3; ++tries) {
+      ++refills;
+      PFE_HIP(pfe::gaussian_fill_f64(n, b, B, ldv, o.seed + 1000003ull * (uint64_t)(refills + 1), h->stream));
+      PFE_TRY(project(B, p0));
+      e = cholqr2(h, sm, B, n, b, ldv, -1.0);
+    }
+    return e;
+  };
+  PFE_HIP(pfe::gaussian_fill_f64(n, b, V, ldv, o.seed, h->stream));
+  {
+    Timer tm(h, &st.t_orth);
+    PFE_TRY(orth_block(V, 0, V));
+  }
+  const int M1 = m + b;
+  std::vector<double> T((size_t)M1 * M1, 0.0), Cf((size_t)M1 * b), th(m), Q((size_t)m * m);
+  std::vector<double> Tm((size_t)m * m);
+  int p = b;                       // columns [p - b, p) still need their filtered image
+  double epsA = 0.1 * tol;         // A-residual target relative to rho(gamma)
+  int prev_nw = -1, cycles = 0, tightened = 0;
+  const double delta = 1e-6 * h->lam_ub;
+  std::vector<double> theta, res;
+  bool done = false;
+  int ns_final = 0;
+  std::vector<int> sel;
+  while (!done) {
+    // ---- expansion to m columns plus the residual block
+    while (p < m + b) {
+      if (p % b != 0 || p + b > M1)
+        return pfe::fail(PFE_EHIP, "internal: Lanczos block outside the basis");
+      {
+        Timer tm(h, &st.t_filter);
+        PFE_TRY(run_filter<double>(h, h->step_vals64(), dd.coef, 1.0 / dd.e, -dd.c / dd.e,
+                                   V + (p - b), V + p, Scr, b, ldv, &st.filter_steps));
+      }
+      st.filter_columns += b;
+      PFE_HIP(pfe::copy_cols_f64(n, b, V + p, ldv, Wk, ldk, h->stream));
+      {
+        Timer tm(h, &st.t_orth);
+        PFE_TRY(orth_block(V, p, V + p));
+        PFE_HIP(pfe::gram_f64(n, p + b, b, V, ldv, Wk, ldk, sm.G, h->wsRed.p, h->stream));
+        PFE_HIP(hipMemcpyAsync(Cf.data(), sm.G, (size_t)(p + b) * b * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+        PFE_TRY(sync(h));
+      }
+      for (int r = 0; r < p + b; ++r)
+        for (int c = 0; c < b; ++c) {
+          const double v = Cf[(size_t)r * b + c];
+          T[(size_t)r * M1 + (p - b + c)] = v;
+          T[(size_t)(p - b + c) * M1 + r] = v;
+        }
+      p += b;
+    }
+    // ---- Ritz pairs of T_m (device Jacobi)
+    for (int r = 0; r < m; ++r)
+      for (int c = 0; c < m; ++c) Tm[(size_t)r * m + c] = T[(size_t)r * M1 + c];
+    int info = 0;
+    {
+      Timer tm(h, &st.t_rr);
+      PFE_HIP(hipMemcpyAsync(sm.S, Tm.data(), Tm.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+      PFE_HIP(pfe::sym_eig_f64(m, sm.S, sm.theta, sm.Q, sm.jw, sm.info, h->stream));
+      PFE_HIP(hipMemcpyAsync(th.data(), sm.theta, m * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      PFE_HIP(hipMemcpyAsync(Q.data(), sm.Q, Q.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      PFE_HIP(hipMemcpyAsync(&info, sm.info, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+      PFE_TRY(sync(h));
+    }
+    if (info < 0) return pfe::fail(PFE_EHIP, "Jacobi eigensolver did not converge");
+    ++cycles;
+    st.iterations = cycles;
+    // residual norms ||B s_i||, B = T[m:m+b, m-b:m]
+    std::vector<double> rA(m, 0.0);
+    for (int i = 0; i < m; ++i) {
+      double s2 = 0;
+      for (int a = 0; a < b; ++a) {
+        double v = 0;
+        for (int r = 0; r < b; ++r) v += T[(size_t)(m + a) * M1 + (m - b + r)] * Q[(size_t)(m - b + r) * m + i];
+        s2 += v * v;
+      }
+      rA[i] = std::sqrt(s2);
+    }
+    // wanted: theta >= tau, largest first (theta ascending from Jacobi)
+    std::vector<int> want;
+    for (int i = m - 1; i >= 0; --i)
+      if (th[i] >= dd.tau) want.push_back(i);
+    const int nw = (int)want.size();
+    if (nw > m - 2 * b) {
+      *n_found = nw;
+      return pfe::fail(PFE_ECAPACITY, "max_basis too small for the eigenvalues above tau");
+    }
+    bool conv = true;
+    for (int i : want) conv = conv && rA[i] <= epsA * dd.peak;
+    const char* tr_env = std::getenv("PFEIG_TRACE");
+    if (tr_env && tr_env[0] && tr_env[0] != '0') {
+      double mx = 0;
+      for (int i : want) mx = std::max(mx, rA[i] / dd.peak);
+      std::fprintf(stderr, "[pfeig] lanczos cycle %d wanted %d max rel A-resid %.3e\n", cycles, nw, mx);
+    }
+    if (conv && nw == prev_nw && cycles >= 2) {
+      // ---- extraction: Rayleigh-Ritz on H over the wanted Ritz vectors
+      if (nw == 0) {
+        theta.clear();
+        res.clear();
+        done = true;
+        break;
+      }
+      std::vector<double> Mw((size_t)m * nw);
+      for (int r = 0; r < m; ++r)
+        for (int c = 0; c < nw; ++c) Mw[(size_t)r * nw + c] = Q[(size_t)r * m + want[c]];
+      PFE_HIP(hipMemcpyAsync(sm.Rinv, Mw.data(), Mw.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+      PFE_HIP(pfe::gemm_tall_f64(n, m, nw, V, ldv, sm.Rinv, Scr, ldv, h->stream));
+      {
+        Timer tm(h, &st.t_orth);
+        PFE_TRY(cholqr2(h, sm, Scr, n, nw, ldv, -1.0));
+      }
+      PFE_TRY(rayleigh_ritz(h, sm, Scr, Wx, n, nw, ldv, theta, res, &st.t_rr, &st.t_resid));
+      bool ok = true;
+      for (int j = 0; j < nw; ++j)
+        if (theta[j] >= lam_lo - delta && theta[j] <= lam_hi + delta) ok = ok && res[j] <= tol;
+      if (ok) {
+        done = true;
+        break;
+      }
+      if (++tightened > 4) return pfe::fail(PFE_ENOCONV, "H residuals above tol after tightening");
+      epsA *= 0.01;
+    }
+    prev_nw = nw;
+    if (cycles >= max_restarts) return pfe::fail(PFE_ENOCONV, "not converged within max_restarts");
+    // ---- thick restart: keep the k largest Ritz vectors, k a multiple of b
+    // so that the expansion fills the basis exactly up to m + b columns
+    const int k = std::min(m - b, (int)round_up(std::max(nw + b, 2 * b), b));
+    std::vector<double> Mk((size_t)m * k);
+    for (int r = 0; r < m; ++r)
+      for (int c = 0; c < k; ++c) Mk[(size_t)r * k + c] = Q[(size_t)r * m + (m - 1 - c)];
+    PFE_HIP(hipMemcpyAsync(sm.Rinv, Mk.data(), Mk.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    PFE_HIP(pfe::gemm_tall_f64(n, m, k, V, ldv, sm.Rinv, V, ldv, h->stream));
+    PFE_HIP(pfe::copy_cols_f64(n, b, V + m, ldv, V + k, ldv, h->stream));
+    std::vector<double> Tn((size_t)M1 * M1, 0.0);
+    for (int c = 0; c < k; ++c) Tn[(size_t)c * M1 + c] = th[m - 1 - c];
+    for (int a = 0; a < b; ++a)
+      for (int c = 0; c < k; ++c) {
+        double v = 0;
+        for (int r = 0; r < b; ++r) v += T[(size_t)(m + a) * M1 + (m - b + r)] * Q[(size_t)(m - b + r) * m + (m - 1 - c)];
+        Tn[(size_t)(k + a) * M1 + c] = v;
+        Tn[(size_t)c * M1 + (k + a)] = v;
+      }
+    T.swap(Tn);
+    p = k + b;
+  }
+  // ---- selection and output (theta ascending)
+  sel.clear();
+  int total_in = 0;
+  for (size_t j = 0; j < theta.size(); ++j)
+    if (theta[j] >= lam_lo && theta[j] <= lam_hi) {
+      ++total_in;
+      sel.push_back((int)j);
+    }
+  st.n_window = total_in;
+  st.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st_out) *st_out = st;
+  if (total_in > nev) {
+    *n_found = total_in;
+    return pfe::fail(PFE_ECAPACITY, "more eigenvalues in the window than nev");
+  }
+  ns_final = (int)sel.size();
+  *n_found = ns_final;
+  double maxr = 0;
+  for (int s2 = 0; s2 < ns_final; ++s2) {
+    if (evals) evals[s2] = theta[sel[s2]];
+    if (resid) resid[s2] = res[sel[s2]];
+    maxr = std::max(maxr, res[sel[s2]]);
+  }
+  if (evecs && ns_final > 0) {
+    PFE_HIP(hipMemcpyAsync(sm.sel, sel.data(), ns_final * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    const bool dev_out = (o.flags & PFE_DEVICE_PTRS) != 0;
+    double* dst = evecs;
+    if (!dev_out) {
+      PFE_HIP(h->wsOut.ensure((size_t)ns_final * n * sizeof(double)));
+      dst = h->wsOut.as<double>();
+    }
+    PFE_HIP(pfe::gather_transpose_signfix(n, ns_final, Scr, ldv, sm.sel, dst, h->wsRed.p, h->stream));
+    if (!dev_out)
+      PFE_HIP(hipMemcpyAsync(evecs, dst, (size_t)ns_final * n * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+    PFE_TRY(sync(h));
+  }
+  st.max_resid = maxr;
+  st.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st_out) *st_out = st;
+  return pfe::ok();
+}
+
+void pfe_lanczos_opts_default(pfe_lanczos_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->block = 16;
+  o->phi = 0.8;
+  o->smoothing = PFE_SMOOTH_NONE;
+  o->max_restarts = 200;
+  o->seed = 11;
+}
+
+pfe_status pfe_solve_lanczos(pfe_handle h, double lam_lo, double lam_hi, int32_t nev,
+                             const pfe_lanczos_opts* opts, int32_t* n_found, double* evals,
+                             double* evecs, double* resid, pfe_solve_stats* stats) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, lanczos_impl(h, lam_lo, lam_hi, nev, opts, n_found, evals, evecs, resid, stats));
+}
+
+pfe_status pfe_design_dirac(double lam_lo, double lam_hi, double lam_lb, double lam_ub,
+                            int32_t degree, double phi, int32_t smoothing, double* coef_out,
+                            int32_t coef_cap, pfe_dirac_filter* out) {
+  if (!out) return PFE_EINVAL;
+  pfe::DiracDesign dd;
+  const Err e = pfe::design_dirac(lam_lo, lam_hi, lam_lb, lam_ub, degree, phi, smoothing, &dd);
+  if (e) return e.st;
+  out->degree = dd.degree;
+  out->smoothing = dd.smoothing;
+  out->c = dd.c;
+  out->e = dd.e;
+  out->xi = dd.xi;
+  out->eta = dd.eta;
+  out->gamma = dd.gamma;
+  out->tau = dd.tau;
+  out->peak = dd.peak;
+  out->coef = coef_out;
+  if (!coef_out || coef_cap < dd.degree + 1) return PFE_ECAPACITY;
+  std::copy(dd.coef.begin(), dd.coef.end(), coef_out);
+  return PFE_OK;
+}
+
 // ---------------------------------------------------------------- adjoint
 static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const double* X,
                         const double* dY, double* dX, double* dblocks, int64_t ld, int stride,

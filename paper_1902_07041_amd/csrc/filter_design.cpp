@@ -210,4 +210,78 @@ Err design_filter(double lam_lo, double lam_hi, double lam_lb, double lam_ub, in
   return ok();
 }
 
+// ------------------------------------------------------------- Dirac filter
+// rho_k(x) = sum_j g_j T_j(gamma) T_j(x) / <T_j, T_j> (eq. cheby-delta.1 with
+// the damping factors g_j of Sec. 2.3), the degree-k stand-in for the Dirac
+// distribution at gamma.  gamma in (xi, eta) is balanced so that
+// rho_k(xi) = rho_k(eta) (Sec. 2.5), by bisection on rho_k(xi) - rho_k(eta),
+// which is positive at gamma = xi and negative at gamma = eta.
+std::vector<double> dirac_coef(double gamma, int k, int smoothing) {
+  std::vector<double> Tg = cheb_T(std::min(1.0, std::max(-1.0, gamma)), k);
+  const std::vector<double> g = damping_factors(smoothing, k);
+  std::vector<double> c(k + 1);
+  for (int j = 0; j <= k; ++j) c[j] = g[j] * Tg[j] / (j == 0 ? kPi : 0.5 * kPi);
+  return c;
+}
+
+static double dirac_gamma(double xi, double eta, int k, int smoothing, int iters) {
+  auto f = [&](double gm) {
+    const std::vector<double> c = dirac_coef(gm, k, smoothing);
+    return cheb_value(c, xi) - cheb_value(c, eta);
+  };
+  double a = xi, b = eta;
+  const double fa = f(a);
+  for (int it = 0; it < iters; ++it) {
+    const double m = 0.5 * (a + b);
+    const double fm = f(m);
+    if (fm == 0.0) return m;
+    if ((fm > 0) == (fa > 0))
+      a = m;
+    else
+      b = m;
+  }
+  return 0.5 * (a + b);
+}
+
+Err design_dirac(double lam_lo, double lam_hi, double lam_lb, double lam_ub, int degree,
+                 double phi, int smoothing, DiracDesign* out) {
+  if (!(lam_ub > lam_lb) || !std::isfinite(lam_lb) || !std::isfinite(lam_ub))
+    return fail(PFE_EINVAL, "bounds must satisfy lam_lb < lam_ub");
+  if (!(lam_hi > lam_lo) || !std::isfinite(lam_lo) || !std::isfinite(lam_hi))
+    return fail(PFE_EINVAL, "window must satisfy lam_lo < lam_hi");
+  if (smoothing < 0 || smoothing > 2) return fail(PFE_EINVAL, "unknown smoothing");
+  if (degree < 0) return fail(PFE_EINVAL, "degree must be >= 0");
+  if (degree == 0 && !(phi > 0 && phi < 1)) return fail(PFE_EINVAL, "phi must lie in (0, 1)");
+  const double c = 0.5 * (lam_ub + lam_lb), e = 0.5 * (lam_ub - lam_lb);
+  const double xi = (lam_lo - c) / e, eta = (lam_hi - c) / e;
+  if (xi < -1.0 || eta > 1.0) return fail(PFE_EINVAL, "window must lie inside the spectral bounds");
+  DiracDesign d;
+  d.c = c;
+  d.e = e;
+  d.xi = xi;
+  d.eta = eta;
+  d.smoothing = smoothing;
+  d.phi = phi;
+  int k = degree;
+  double gm = 0.5 * (xi + eta);
+  if (k == 0) {
+    // smallest k with rho_k(xi) / rho_k(gamma) <= phi (Sec. 4.1 tables)
+    const int kmax = 20000;
+    for (k = 1; k <= kmax; ++k) {
+      gm = dirac_gamma(xi, eta, k, smoothing, 60);
+      const std::vector<double> cf = dirac_coef(gm, k, smoothing);
+      const double top = cheb_value(cf, gm);
+      if (top > 0 && cheb_value(cf, xi) / top <= phi) break;
+    }
+    if (k > kmax) return fail(PFE_EINVAL, "no Dirac degree up to 20000 reaches phi");
+  }
+  d.degree = k;
+  d.gamma = dirac_gamma(xi, eta, k, smoothing, 200);
+  d.coef = dirac_coef(d.gamma, k, smoothing);
+  d.tau = cheb_value(d.coef, xi);
+  d.peak = cheb_value(d.coef, d.gamma);
+  *out = std::move(d);
+  return ok();
+}
+
 }  // namespace pfe

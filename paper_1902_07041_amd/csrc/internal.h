@@ -172,6 +172,9 @@ hipError_t cast_f32_to_f64(int64_t n, int q, const float* X, int64_t ldx, double
 // Y[:, :q] = X[:, :q] (any lds)
 hipError_t copy_cols_f64(int64_t n, int q, const double* X, int64_t ldx, double* Y, int64_t ldy,
                          hipStream_t s);
+// Y[:, :q] -= X[:, :q] (any lds; X and Y must not overlap)
+hipError_t sub_cols_f64(int64_t n, int q, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                        hipStream_t s);
 // Y[:, c] = X[:, perm[c]] (perm a device array of q column indices; X != Y).
 hipError_t permute_cols_f64(int64_t n, int q, const double* X, int64_t ld, const int* perm,
                             double* Y, hipStream_t s);
@@ -239,5 +242,16 @@ Err design_filter(double lam_lo, double lam_hi, double lam_lb, double lam_ub, in
 std::vector<double> chi_coefficients(double a, double b, int degree, int smoothing);
 // value of sum_j coef_j T_j(x) for |x| <= 1
 double cheb_value(const std::vector<double>& coef, double x);
+// Dirac-delta filter of Sec. 2.5 (eq. cheby-delta.1): coefficients, the
+// balanced centre gamma, tau = rho(xi) = rho(eta) and the peak rho(gamma).
+// degree 0: smallest degree with tau / peak <= phi.
+struct DiracDesign {
+  int degree = 0;
+  int smoothing = 0;
+  double c = 0, e = 0, xi = 0, eta = 0, gamma = 0, tau = 0, peak = 0, phi = 0;
+  std::vector<double> coef;
+};
+Err design_dirac(double lam_lo, double lam_hi, double lam_lb, double lam_ub, int degree,
+                 double phi, int smoothing, DiracDesign* out);
 
 }  // namespace pfe

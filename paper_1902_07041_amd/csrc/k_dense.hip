@@ -528,6 +528,14 @@ __global__ void k_copy_cols(int64_t n, int q, const double* __restrict__ X, int6
   const int64_t r = i / q, c = i % q;
   Y[r * ldy + c] = X[r * ldx + c];
 }
+// Y[:, :q] -= X[:, :q]
+__global__ void k_sub_cols(int64_t n, int q, const double* __restrict__ X, int64_t ldx,
+                           double* __restrict__ Y, int64_t ldy) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * q) return;
+  const int64_t r = i / q, c = i % q;
+  Y[r * ldy + c] -= X[r * ldx + c];
+}
 // Y[:, c] = X[:, perm[c]] for c < q (column permutation of a row-major block).
 __global__ void k_permute_cols(int64_t n, int q, const double* __restrict__ X, int64_t ld,
                                const int* __restrict__ perm, double* __restrict__ Y) {
@@ -828,6 +836,12 @@ hipError_t copy_cols_f64(int64_t n, int q, const double* X, int64_t ldx, double*
                          hipStream_t s) {
   if (n * q == 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_cols, dim3(nblocks(n * q, 256)), dim3(256), 0, s, n, q, X, ldx, Y, ldy);
+  return hipGetLastError();
+}
+hipError_t sub_cols_f64(int64_t n, int q, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                        hipStream_t s) {
+  if (n * q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sub_cols, dim3(nblocks(n * q, 256)), dim3(256), 0, s, n, q, X, ldx, Y, ldy);
   return hipGetLastError();
 }
 hipError_t permute_cols_f64(int64_t n, int q, const double* X, int64_t ld, const int* perm,

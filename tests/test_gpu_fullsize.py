@@ -144,3 +144,9 @@ def test_full_hellmann_feynman(full):
     assert rel_err(dk, rk) <= 1e-12
     assert rel_err(dm, rm) <= 1e-12
     assert np.sum(g.k * dk) == pytest.approx(np.sum(w * full.lam[:8]), rel=1e-10)
+
+
+def test_full_lanczos_dirac(full):
+    banner("full TR-Lanczos on the Dirac filter, block 32, basis 224")
+    out = P.pfe_solve_lanczos(full.h, full.lo, full.hi, 96, block=32, max_basis=224, tol=1e-10)
+    _check_solve(full, out, 1e-10, 1e-10)

@@ -68,3 +68,32 @@ def test_design_filter_errors():
         P.pfe_design_filter(0.1, 0.2, 0.0, 1.0)                 # neither degree nor eps
     with pytest.raises(P.PfeError):
         P.pfe_design_filter(0.1, 1.2, 0.0, 1.0, degree=10)      # window beyond the bounds
+
+
+def test_design_dirac_reproduces_table_degrees():
+    """The library's Dirac design (host only) gives the 18 Dirac degrees of
+    Tables 1-3 (phi = 0.8, 0.6 for Jackson, Lanczos and no smoothing)."""
+    t = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_filter_values.json")))
+    smooth = [P.PFE_SMOOTH_JACKSON, P.PFE_SMOOTH_LANCZOS, P.PFE_SMOOTH_NONE]
+    for tab in t["tables"]:
+        for phi, degs in tab["dirac"].items():
+            got = [P.pfe_design_dirac(tab["xi"], tab["eta"], -1.0, 1.0, 0, float(phi), s).degree
+                   for s in smooth]
+            assert got == degs, (tab["_cite"], phi, got, degs)
+
+
+@pytest.mark.parametrize("sm,name", [(P.PFE_SMOOTH_NONE, F.NONE), (P.PFE_SMOOTH_JACKSON, F.JACKSON)])
+def test_design_dirac_matches_oracle(sm, name):
+    lb, ub = 0.0, 2.0
+    lo, hi = 0.11, 0.16
+    f = P.pfe_design_dirac(lo, hi, lb, ub, 120, 0.8, sm)
+    c, e = F.spectral_map(lb, ub)
+    xi, eta = (lo - c) / e, (hi - c) / e
+    g = F.dirac_balance(xi, eta, 120, name)
+    assert f.gamma == pytest.approx(g, abs=1e-12)
+    ref = F.dirac_coefficients(g, 120, name)
+    np.testing.assert_allclose(f.coef, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    vals = F.cheb_eval(ref, [xi, eta, g])
+    assert f.tau == pytest.approx(vals[0], rel=1e-10)
+    assert f.tau == pytest.approx(vals[1], rel=1e-9)
+    assert f.peak == pytest.approx(vals[2], rel=1e-10)

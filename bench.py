@@ -111,6 +111,55 @@ def cpu_baseline(g, H_bounds, stats64, W):
     }
 
 
+def extras(P, sysm, g, last, W, X0):
+    """One timed run each of the solver variants beyond the benchmark step."""
+    import numpy as np
+    import torch
+    h = sysm.h
+    lo, hi, th = last["lo"], last["hi"], last["theta_max"]
+    ev64 = last["o64"]["evals"]
+    res = {}
+    print("[bench] extras: Lanczos on the Dirac filter", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    o = P.pfe_solve_lanczos(h, lo, hi, W["nev"], block=32, max_basis=224, tol=W["tol64"])
+    t = time.perf_counter() - t0
+    st = o["stats"]
+    res["lanczos_dirac"] = {
+        "block": 32, "max_basis": 224, "phi": 0.8, "degree": st["degree"], "seconds": t,
+        "restart_cycles": st["iterations"], "filter_steps": st["filter_steps"],
+        "filter_columns": st["filter_columns"], "n_found": int(o["evals"].size),
+        "max_resid": float(o["resid"].max()),
+        "max_rel_eig_diff_vs_si": float(np.max(np.abs(o["evals"] - ev64) / ev64))
+        if o["evals"].shape == ev64.shape else None}
+    print("[bench] extras: FP64 solve without locking", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    o = P.pfe_solve_interval(h, lo, hi, W["nev"], W["block"], degree=W["degree"], tol=W["tol64"],
+                             x0=X0, locking=0, vectors_on_device=True)
+    res["fp64_no_locking"] = {"seconds": time.perf_counter() - t0,
+                              "iterations": o["stats"]["iterations"],
+                              "filter_columns": o["stats"]["filter_columns"]}
+    print("[bench] extras: count estimate", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    cnt = P.pfe_estimate_count(h, lo, hi, 1000, P.PFE_SMOOTH_JACKSON, nsamples=32, seed=13)
+    res["count_estimate"] = {"window_count": int(ev64.size), "estimate": cnt, "degree": 1000,
+                             "probes": 32, "seconds": time.perf_counter() - t0}
+    lo2, hi2 = 0.005 * th, 0.015 * th
+    print("[bench] extras: sliced solve of [0.5%, 1.5%] theta_max", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    o = P.pfe_solve_sliced(h, lo2, hi2, 1024, W["block"], per_slice=48, tol=W["tol64"],
+                           want_vectors=True, vectors_on_device=True)
+    t = time.perf_counter() - t0
+    V = o["evecs"]
+    G = (V @ V.T.contiguous()).cpu().numpy() if V is not None and V.shape[0] else np.zeros((0, 0))
+    res["sliced_literal_window"] = {
+        "window_frac_theta": [0.005, 0.015], "seconds": t, "n_found": int(o["evals"].size),
+        "n_slices": o["n_slices"], "iterations_total": o["stats"]["iterations"],
+        "filter_steps": o["stats"]["filter_steps"], "max_resid": float(o["resid"].max()),
+        "max_offdiag_overlap": float(np.abs(G - np.eye(G.shape[0])).max()) if G.size else None}
+    return res
+
+
 def copy_calibration() -> int:
     """Device-to-device copy of 2 GiB (reads 2 GiB, writes 2 GiB per copy):
     the scale for FETCH_SIZE / WRITE_SIZE counters and the achievable copy
@@ -140,6 +189,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extras", action="store_true",
+                    help="after the timed steps, also time the rows beyond the hot path once: "
+                         "thick-restart Lanczos on the Dirac filter, spectrum slicing of the "
+                         "literal window [0.5%%, 1.5%%] theta_max, locking off, the count estimate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 2 GiB device buffer 5 times and print the copy bandwidth "
                          "(the reference for the HBM traffic counters)")
@@ -297,6 +350,8 @@ def main() -> int:
                      "avg_launch_us": 1e6 * avg_launch,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
+    if args.extras:
+        out["extras"] = extras(P, sysm, g, last, W, X0)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, (last["lam_lb"], last["lam_ub"]), s64, W)
     sysm.close()

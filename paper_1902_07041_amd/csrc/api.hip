@@ -876,7 +876,9 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     PFE_HIP(pfe::gaussian_fill_f64(n, q, X, ld, o.seed, h->stream));
   }
   if (mixed) PFE_TRY(ensure_h32(h, fd.c, fd.e));
-  const double bound = 1.05 * coef_abs_sum(fd.coef) + 1e-12;
+  double bound = 1.05 * coef_abs_sum(fd.coef) + 1e-12;
+  int stall = 0;
+  const int max_degree = std::min(200000, 8 * std::max(fd.degree, 1));
   {
     Timer tm(h, &st.t_orth);
     PFE_TRY(cholqr2(h, sm, X, n, q, ld, -1.0));
@@ -981,9 +983,27 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       converged = true;
       break;
     }
+    // A plateau far above the FP32 rounding level means the filter cannot
+    // separate the window from eigenvalues in its margin (the block holds
+    // fewer vectors than [xi - eps, eta + eps] has eigenvalues, Sec. 2.6):
+    // raise the degree 1.5-fold, which shrinks eps by eq. thresh.
+    const bool plateau = it >= 3 && cnt == prev_cnt && mx > 0.7 * prev_max;
+    stall = plateau ? stall + 1 : 0;
+    const double stall_floor = fp64_phase ? o.tol : 1e-5;
+    if (stall >= 3 && mx > stall_floor && !(fp64_phase && st.refined) &&
+        fd.degree < max_degree) {
+      const int nd = std::min(max_degree, (int)std::ceil(1.5 * fd.degree));
+      PFE_TRY(pfe::design_filter(lam_lo, lam_hi, h->lam_lb, h->lam_ub, nd, 0.0, o.r, o.smoothing, &fd));
+      bound = 1.05 * coef_abs_sum(fd.coef) + 1e-12;
+      st.degree = fd.degree;
+      st.eps = fd.eps;
+      stall = 0;
+      if (trace) std::fprintf(stderr, "[pfeig] plateau: degree raised to %d (eps %.3e)\n", fd.degree, fd.eps);
+    }
     if (!fp64_phase && it >= 2 && cnt == prev_cnt &&
-        (mx > 0.5 * prev_max || mx <= 30.0 * o.tol)) {
-      // FP32 iterations have stalled (or are within reach of tol): one FP64 sweep
+        ((mx > 0.5 * prev_max && mx <= 1e-5) || mx <= 30.0 * o.tol)) {
+      // FP32 iterations have stalled at their rounding level (or are within
+      // reach of tol): one FP64 sweep
       fp64_phase = true;
       st.refined = 1;
     }

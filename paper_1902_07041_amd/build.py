@@ -19,7 +19,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpfeig.so")
-SOURCES = ["api.hip", "k_sparse.hip", "k_dense.hip", "k_adjoint.hip", "filter_design.cpp"]
+SOURCES = ["api.hip", "k_sparse.hip", "k_dense.hip", "k_adjoint.hip", "filter_design.cpp",
+           "reorder.cpp"]
 ARCH = "gfx950"
 
 

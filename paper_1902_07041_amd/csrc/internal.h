@@ -74,25 +74,41 @@ struct Bsr {
   int64_t nnzb = 0;
   const int64_t* row_ptr = nullptr;   // [n_atoms+1]
   const int32_t* col_idx = nullptr;   // [nnzb]
-  // Row tiles (optional, tile_rows >= 2): R = tile_rows consecutive block rows
-  // form a tile.  Tile t owns union columns [tile_ptr[t], tile_ptr[t+1]) of
-  // tile_cm, each a (column, row mask) pair (bit r set when row t*R + r
-  // stores a block in that column), sorted by column.  With tiles active the
-  // fused step reads its block values in tile order: the blocks of tile t
-  // start at tile_vptr[t] and follow (union column, row) order.  tile_cm
-  // carries kBsrPad padded entries.
+  // Row tiles (optional, tile_rows >= 2): tile t holds the R = tile_rows block
+  // rows tile_row[t*R .. t*R+R-1] (-1 past the last row), consecutive in the
+  // processing order of the rows.  Tile t owns union columns
+  // [tile_ptr[t], tile_ptr[t+1]) of tile_cm, each a (column, row mask) pair
+  // (bit r set when row tile_row[t*R + r] stores a block in that column),
+  // sorted by column.  With tiles active the fused step reads its block
+  // values in tile order: the blocks of tile t start at tile_vptr[t] and
+  // follow (union column, tile row) order.  tile_cm carries kBsrPad padded
+  // entries.
   int tile_rows = 0;
   int64_t n_tiles = 0;
   const int64_t* tile_ptr = nullptr;
   const int64_t* tile_vptr = nullptr;
   const int2* tile_cm = nullptr;
+  const int32_t* tile_row = nullptr;
+  bool tile_local = false;   // tile_row follows the locality order (one row range per XCD)
 };
 
-// Host construction of the row tiles of a block-CSR pattern (see Bsr);
-// perm[p] is the row-order index of the block at tile-order position p.
+// Processing order of the atom rows in which contiguous ranges are compact in
+// the graph of the (symmetric) pattern: recursive BFS bisection down to
+// ranges of `leaf` rows (split at multiples of R), and inside each leaf
+// groups of R rows sharing many block columns.
+void locality_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int leaf, int R,
+                    std::vector<int32_t>& order);
+// Fraction of the off-diagonal blocks (i, j) whose rows lie more than
+// `window` positions apart in the processing order `order` (nullptr: natural).
+double far_block_fraction(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                          const int32_t* order, int64_t window);
+// Host construction of the row tiles of a block-CSR pattern (see Bsr), the
+// rows taken R at a time in `order` (nullptr: natural order); perm[p] is the
+// row-order index of the block at tile-order position p.
 void build_row_tiles(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col_idx, int R,
-                     std::vector<int64_t>& tile_ptr, std::vector<int64_t>& tile_vptr,
-                     std::vector<int32_t>& tile_cm, std::vector<int64_t>& perm);
+                     const int32_t* order, std::vector<int64_t>& tile_ptr,
+                     std::vector<int64_t>& tile_vptr, std::vector<int32_t>& tile_cm,
+                     std::vector<int32_t>& tile_row, std::vector<int64_t>& perm);
 // dst[p] = src[perm[p]] for 3x3 blocks (FP64 and FP32).
 hipError_t permute_blocks_f64(int64_t nnzb, const int64_t* perm, const double* src, double* dst,
                               hipStream_t s);
@@ -204,14 +220,11 @@ hipError_t scale_by_inv_f64(int64_t n, const double* x, const double* nrm, doubl
                             hipStream_t s);
 
 // ---------------------------------------------------------- adjoint (K9-K11)
-// out = alpha (H a_in) + beta a_in + delta prev + zeta ybar, and when t is
-// given, G[transpose[b]] += gw * a_in[j] t[i]^T for every stored b = (i, j).
-// q <= 256.  out may alias prev.
-hipError_t adjoint_step_f64(const Bsr& A, const int32_t* transpose, const double* vals,
-                            const double* a_in, const double* prev, const double* ybar,
-                            double* out, const double* t, double* G, int q, int64_t ld,
-                            double alpha, double beta, double delta, double zeta, double gw,
-                            hipStream_t s);
+// G[b] += sum_m w[m] sum_c a_m[3i+p][c] t_m[3j+q][c] for stored b = (i, j), with
+// a_m = a + m a_stride, t_m = t + m t_stride ([n][ld] each), w on the device; q <= 256.
+hipError_t sddmm_seg_f64(const Bsr& A, int q, int m, const double* a, int64_t a_stride,
+                         const double* t, int64_t t_stride, int64_t ld, const double* w,
+                         double* G, hipStream_t s);
 // G[b] (+)= sum_c colw_c a[3i+p][c] t[3j+q][c] for stored b = (i, j); q <= 256.
 hipError_t sddmm_f64(const Bsr& A, int q, const double* a, const double* t, int64_t ld,
                      const double* colw, double* G, bool accumulate, hipStream_t s);

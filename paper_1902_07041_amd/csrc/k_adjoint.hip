@@ -1,13 +1,13 @@
 // Reverse mode of the Chebyshev filter (no counterpart in the paper; it is
 // the chain rule applied to Algorithm 2) and the gradient kernels.
 //
-// Reverse step, one wavefront per atom row i (the forward step's mapping):
-//   out_i = alpha (H a)_i + beta a_i + delta prev_i + zeta ybar_i
-// and, when t != nullptr, the block-gradient contribution
-//   G[(j, i)] += gw * a_j t_i^T      for every stored block (i, j),
-// a 3x3 matrix of dot products over the q columns, reduced across the wave.
-// Block (j, i) is found through the transpose map and is written only by the
-// wave of row i, so the accumulation needs no atomics and is deterministic.
+// The reverse recurrence itself runs on the fused filter step (H_hat is
+// symmetric).  The block gradient G_b = sum_k w_k a_{k+1}[i] t_k[j]^T over
+// the stored blocks b = (i, j) is an SDDMM: one wavefront per atom row i, the
+// three rows of the wave's own atom against the three rows of each
+// neighbour, a 3x3 matrix of dot products over the q columns reduced across
+// the wave.  Every block is written only by the wave of its row, so the
+// accumulation needs no atomics and is deterministic.
 #include "internal.h"
 
 namespace pfe {
@@ -19,86 +19,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
-}
-
-// Columns per lane: NP passes of one double (chunk = lane + 64 p).
-template <int NP>
-__global__ __launch_bounds__(256) void k_adj_step(
-    int n_atoms, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-    const int32_t* __restrict__ transpose, const double* __restrict__ vals,
-    const double* __restrict__ a_in, const double* prev, const double* __restrict__ ybar,
-    double* out, const double* __restrict__ t, double* G, int q, int64_t ld, double alpha,
-    double beta, double delta, double zeta, double gw) {
-  const int wave = uniform(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int row = uniform(blockIdx.x * 4 + wave);
-  if (row >= n_atoms) return;
-  double acc[3][NP], tr[3][NP];
-  bool act[NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    act[p] = lane + 64 * p < q;
-    for (int a = 0; a < 3; ++a) {
-      acc[a][p] = 0.0;
-      tr[a][p] = 0.0;
-    }
-  }
-  const bool grad = (t != nullptr);
-  if (grad) {
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-      if (act[p])
-        for (int a = 0; a < 3; ++a) tr[a][p] = t[(int64_t)(3 * row + a) * ld + lane + 64 * p];
-  }
-  const int64_t b0 = row_ptr[row], b1 = row_ptr[row + 1];
-  for (int64_t k = b0; k < b1; ++k) {
-    const int j = col_idx[k];
-    const double* hv = vals + k * 9;
-    double h[9];
-#pragma unroll
-    for (int s = 0; s < 9; ++s) h[s] = hv[s];
-    double x[3][NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      for (int a = 0; a < 3; ++a)
-        x[a][p] = act[p] ? a_in[(int64_t)(3 * j + a) * ld + lane + 64 * p] : 0.0;
-      acc[0][p] += h[0] * x[0][p] + h[1] * x[1][p] + h[2] * x[2][p];
-      acc[1][p] += h[3] * x[0][p] + h[4] * x[1][p] + h[5] * x[2][p];
-      acc[2][p] += h[6] * x[0][p] + h[7] * x[1][p] + h[8] * x[2][p];
-    }
-    if (grad) {
-      const int tb = transpose[k];
-      double g[9];
-#pragma unroll
-      for (int pa = 0; pa < 3; ++pa)
-#pragma unroll
-        for (int qb = 0; qb < 3; ++qb) {
-          double s = 0.0;
-#pragma unroll
-          for (int p = 0; p < NP; ++p) s += x[pa][p] * tr[qb][p];
-          g[pa * 3 + qb] = wave_sum(s);
-        }
-      if (lane < 9) {
-        double v = 0.0;
-#pragma unroll
-        for (int s = 0; s < 9; ++s)
-          if (lane == s) v = g[s];
-        G[(int64_t)tb * 9 + lane] += gw * v;
-      }
-    }
-  }
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    if (!act[p]) continue;
-    for (int a = 0; a < 3; ++a) {
-      const int64_t off = (int64_t)(3 * row + a) * ld + lane + 64 * p;
-      double o = alpha * acc[a][p];
-      if (beta != 0.0) o += beta * a_in[off];
-      if (delta != 0.0) o += delta * prev[off];
-      if (zeta != 0.0) o += zeta * ybar[off];
-      out[off] = o;
-    }
-  }
 }
 
 // G[b] (+)= sum_c w_c a[3i+p][c] t[3j+q][c] for stored b = (i, j): rows of a
@@ -150,6 +70,61 @@ __global__ __launch_bounds__(256) void k_sddmm(int n_atoms, const int64_t* __res
       else
         G[k * 9 + lane] = v;
     }
+  }
+}
+
+// Block gradient of a whole checkpoint segment in one pass:
+//   G[b] (+)= sum_m w_m sum_c a_m[3i+p][c] t_m[3j+q][c]   for stored b = (i, j),
+// with a_m = A + m * a_stride (rows of the wave's own atom i) and
+// t_m = T + m * t_stride (rows of the neighbour j).  Every lane keeps its
+// nine partial sums over all m pairs, so each block is reduced across the
+// wave once per segment instead of once per recurrence step.
+template <int NP>
+__global__ __launch_bounds__(256) void k_sddmm_seg(int n_atoms, const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col_idx, int q, int m,
+                                                   const double* __restrict__ A, int64_t a_stride,
+                                                   const double* __restrict__ T, int64_t t_stride,
+                                                   int64_t ld, const double* __restrict__ w,
+                                                   double* G) {
+  const int wave = uniform(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int row = uniform(blockIdx.x * 4 + wave);
+  if (row >= n_atoms) return;
+  bool act[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) act[p] = lane + 64 * p < q;
+  for (int64_t k = row_ptr[row]; k < row_ptr[row + 1]; ++k) {
+    const int j = col_idx[k];
+    double g[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) g[e] = 0.0;
+    for (int mm = 0; mm < m; ++mm) {
+      const double wm = w[mm];
+      const double* am = A + mm * a_stride;
+      const double* tm = T + mm * t_stride;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        if (!act[p]) continue;
+        const int c = lane + 64 * p;
+        double ar[3], tr[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          ar[r] = wm * am[(int64_t)(3 * row + r) * ld + c];
+          tr[r] = tm[(int64_t)(3 * j + r) * ld + c];
+        }
+#pragma unroll
+        for (int pa = 0; pa < 3; ++pa)
+#pragma unroll
+          for (int qb = 0; qb < 3; ++qb) g[pa * 3 + qb] += ar[pa] * tr[qb];
+      }
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      const double tot = wave_sum(g[e]);
+      if (lane == e) v = tot;
+    }
+    if (lane < 9) G[k * 9 + lane] += v;
   }
 }
 
@@ -290,30 +265,6 @@ inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
-hipError_t adjoint_step_f64(const Bsr& A, const int32_t* transpose, const double* vals,
-                            const double* a_in, const double* prev, const double* ybar,
-                            double* out, const double* t, double* G, int q, int64_t ld,
-                            double alpha, double beta, double delta, double zeta, double gw,
-                            hipStream_t s) {
-  if (A.n_atoms == 0 || q == 0) return hipSuccess;
-  const unsigned grid = nb(A.n_atoms, 4);
-  if (q <= 64)
-    hipLaunchKernelGGL(k_adj_step<1>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
-                       A.col_idx, transpose, vals, a_in, prev, ybar, out, t, G, q, ld, alpha,
-                       beta, delta, zeta, gw);
-  else if (q <= 128)
-    hipLaunchKernelGGL(k_adj_step<2>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
-                       A.col_idx, transpose, vals, a_in, prev, ybar, out, t, G, q, ld, alpha,
-                       beta, delta, zeta, gw);
-  else if (q <= 256)
-    hipLaunchKernelGGL(k_adj_step<4>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
-                       A.col_idx, transpose, vals, a_in, prev, ybar, out, t, G, q, ld, alpha,
-                       beta, delta, zeta, gw);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
 hipError_t sddmm_f64(const Bsr& A, int q, const double* a, const double* t, int64_t ld,
                      const double* colw, double* G, bool accumulate, hipStream_t s) {
   if (A.n_atoms == 0) return hipSuccess;
@@ -352,6 +303,25 @@ hipError_t assemble_springs(int64_t n_atoms, const int64_t* row_ptr, const int32
   if (n_atoms > 0)
     hipLaunchKernelGGL(k_assemble_springs, dim3(nb(n_atoms, 256)), dim3(256), 0, s, (int)n_atoms,
                        row_ptr, col_idx, P, pairs, unit, k, K, err);
+  return hipGetLastError();
+}
+
+hipError_t sddmm_seg_f64(const Bsr& A, int q, int m, const double* a, int64_t a_stride,
+                         const double* t, int64_t t_stride, int64_t ld, const double* w,
+                         double* G, hipStream_t s) {
+  if (A.n_atoms == 0 || m == 0) return hipSuccess;
+  const unsigned grid = nb(A.n_atoms, 4);
+  if (q <= 64)
+    hipLaunchKernelGGL(k_sddmm_seg<1>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
+                       A.col_idx, q, m, a, a_stride, t, t_stride, ld, w, G);
+  else if (q <= 128)
+    hipLaunchKernelGGL(k_sddmm_seg<2>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
+                       A.col_idx, q, m, a, a_stride, t, t_stride, ld, w, G);
+  else if (q <= 256)
+    hipLaunchKernelGGL(k_sddmm_seg<4>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
+                       A.col_idx, q, m, a, a_stride, t, t_stride, ld, w, G);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -264,8 +264,9 @@ template <typename T, int VW, int NP, int U, int R>
 __global__ __launch_bounds__(256) void k_cheb_tile(
     int n_atoms, int n_tiles, const int64_t* __restrict__ tile_ptr,
     const int64_t* __restrict__ tile_vptr, const int2* __restrict__ tile_cm,
-    const T* __restrict__ vals, const T* __restrict__ tin, const T* prev, const T* add, T* out,
-    int q, int64_t ld, T alpha, T beta, T delta, T zeta, int chunk) {
+    const int32_t* __restrict__ tile_row, const T* __restrict__ vals,
+    const T* __restrict__ tin, const T* prev, const T* add, T* out, int q, int64_t ld, T alpha,
+    T beta, T delta, T zeta, int chunk) {
   using vt = typename VT<T, VW>::type;
   const int lb = map_block(blockIdx.x, chunk);
   const int wave = uniform(threadIdx.x >> 6);
@@ -288,7 +289,10 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
   const int64_t u0 = tile_ptr[tile];
   const int64_t u1 = (alpha != T(0)) ? tile_ptr[tile + 1] : u0;
   int64_t voff = tile_vptr[tile];
-  const int own = tile * R;
+  int rows[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) rows[r] = tile_row[tile * R + r];   // -1: no row
+  const int own = rows[0];
   for (int64_t k = u0; k < u1; k += U) {
     vt x[U][3][NP];
     int2 cm[U];
@@ -337,8 +341,8 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int row = own + r;
-    if (row < n_atoms)
+    const int row = rows[r];
+    if (row >= 0)
       step_epilogue<T, VW, NP>(acc[r], act, row, lane, col0, tin, prev, add, out, ld, alpha,
                                beta, delta, zeta);
   }
@@ -376,24 +380,30 @@ hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev,
   const int64_t units = (R >= 2) ? A.n_tiles : A.n_atoms;   // one wave per unit
   const int64_t nblk = (units + kWavesPerBlock - 1) / kWavesPerBlock;
   const int64_t per_xcd = (nblk + 7) / 8;
-  int chunk = chunk_override() > 0 ? chunk_override() : PFE_CHEB_CHUNK;
-  if (R >= 2) chunk = std::max(1, chunk / R);   // keep rows per chunk comparable
+  // rows in locality order: one contiguous range (a compact region) per XCD;
+  // natural order: chunks of PFE_CHEB_CHUNK work-groups dealt round-robin
+  int chunk = (R >= 2 && A.tile_local) ? 0 : PFE_CHEB_CHUNK;
+  if (chunk_override() >= 0) chunk = chunk_override();
+  if (R >= 2) chunk = std::max(chunk > 0 ? 1 : 0, chunk / R);   // keep rows per chunk comparable
   if (chunk <= 0 || chunk > per_xcd) chunk = (int)per_xcd;
   const int64_t grid_x = ((nblk + 8LL * chunk - 1) / (8LL * chunk)) * 8LL * chunk;
   const int cols_per_group = 64 * NP * VW;
   dim3 grid((unsigned)grid_x, (unsigned)((q + cols_per_group - 1) / cols_per_group));
   if (R == 2) {
     hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 2>), grid, dim3(256), 0, s,
-                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm, vals,
-                       tin, prev, add, out, q, ld, alpha, beta, delta, zeta, chunk);
+                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
+                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, beta, delta, zeta,
+                       chunk);
   } else if (R == 3) {
     hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 3>), grid, dim3(256), 0, s,
-                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm, vals,
-                       tin, prev, add, out, q, ld, alpha, beta, delta, zeta, chunk);
+                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
+                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, beta, delta, zeta,
+                       chunk);
   } else if (R == 4) {
     hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 4>), grid, dim3(256), 0, s,
-                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm, vals,
-                       tin, prev, add, out, q, ld, alpha, beta, delta, zeta, chunk);
+                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
+                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, beta, delta, zeta,
+                       chunk);
   } else if (PFE_CHEB_VARIANT == 1) {
     hipLaunchKernelGGL((k_cheb_step_lds<T, VW, NP, kUnroll>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, ld,
@@ -617,22 +627,26 @@ hipError_t validate_masses(int64_t n_atoms, const double* masses, int* err_flags
 }
 
 void build_row_tiles(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col_idx, int R,
-                     std::vector<int64_t>& tile_ptr, std::vector<int64_t>& tile_vptr,
-                     std::vector<int32_t>& tile_cm, std::vector<int64_t>& perm) {
+                     const int32_t* order, std::vector<int64_t>& tile_ptr,
+                     std::vector<int64_t>& tile_vptr, std::vector<int32_t>& tile_cm,
+                     std::vector<int32_t>& tile_row, std::vector<int64_t>& perm) {
   const int64_t n_tiles = (n_atoms + R - 1) / R;
   tile_ptr.assign(n_tiles + 1, 0);
   tile_vptr.assign(n_tiles, 0);
+  tile_row.assign(n_tiles * R, -1);
   tile_cm.clear();
   perm.clear();
   perm.reserve(row_ptr[n_atoms]);
   std::vector<std::pair<int32_t, int64_t>> ent;   // (column, r << 40 | block)
   for (int64_t t = 0; t < n_tiles; ++t) {
     ent.clear();
-    const int64_t r0 = t * R, r1 = std::min<int64_t>(r0 + R, n_atoms);
-    for (int64_t row = r0; row < r1; ++row)
+    for (int r = 0; r < R && t * R + r < n_atoms; ++r) {
+      const int64_t row = order ? order[t * R + r] : t * R + r;
+      tile_row[t * R + r] = (int32_t)row;
       for (int64_t b = row_ptr[row]; b < row_ptr[row + 1]; ++b)
-        ent.emplace_back(col_idx[b], ((row - r0) << 40) | b);
-    std::sort(ent.begin(), ent.end());   // by column, then row
+        ent.emplace_back(col_idx[b], ((int64_t)r << 40) | b);
+    }
+    std::sort(ent.begin(), ent.end());   // by column, then tile row
     tile_vptr[t] = (int64_t)perm.size();
     int64_t nu = 0;
     for (size_t e = 0; e < ent.size();) {

@@ -166,6 +166,29 @@ def assemble_blocks(N: int, pairs: np.ndarray, unit: np.ndarray, k: np.ndarray):
     return row_ptr, cols.astype(np.int32), np.ascontiguousarray(vals)
 
 
+def relabel(g: Glass, seed: int) -> Glass:
+    """The same glass with its atoms renumbered by a seeded random permutation,
+    as atom ids of a molecular-dynamics snapshot carry no spatial order: new
+    atom a is old atom ``perm[a]``.  Springs keep their constants and are
+    re-sorted as (i, j), i < j; a unit vector flips with its pair's ends."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    N = g.n_atoms
+    perm = rng.permutation(N)
+    inv = np.empty(N, dtype=np.int64)
+    inv[perm] = np.arange(N, dtype=np.int64)
+    a, b = inv[g.pairs[:, 0]], inv[g.pairs[:, 1]]
+    swap = a > b
+    lo, hi = np.where(swap, b, a), np.where(swap, a, b)
+    unit = np.where(swap[:, None], -g.unit, g.unit)
+    order = np.lexsort((hi, lo))
+    pairs = np.stack([lo[order], hi[order]], axis=1)
+    unit, k = np.ascontiguousarray(unit[order]), g.k[order]
+    row_ptr, col_idx, blocks = assemble_blocks(N, pairs, unit, k)
+    return Glass(n_atoms=N, box=g.box, spacing=g.spacing, positions=g.positions[perm],
+                 masses=g.masses[perm], pairs=pairs, unit=unit, k=k, row_ptr=row_ptr,
+                 col_idx=col_idx, blocks=blocks)
+
+
 def offdiag_count(g: Glass) -> float:
     """Mean number of spring neighbours per atom."""
     return 2.0 * g.pairs.shape[0] / g.n_atoms

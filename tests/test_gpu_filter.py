@@ -4,8 +4,8 @@ import numpy as np
 import pytest
 
 import paper_1902_07041_amd as P
-from oracle import chebyshev, filters as F, lanczos
-from synth import gaussian_block, gaussian_vector
+from oracle import chebyshev, filters as F, hessian, lanczos
+from synth import gaussian_block, gaussian_vector, relabel
 
 from gpu_common import GlassCase, banner, rel_err
 
@@ -136,3 +136,36 @@ def test_filter_row_tile_variants(case, tile_rows, q, monkeypatch):
             assert rel_err(Y, ref) < (1e-12 if prec == np.float64 else 5e-5)
     finally:
         P.pfe_destroy(h)
+
+
+@pytest.mark.parametrize("tile_rows", ["2", "3"])
+@pytest.mark.parametrize("numbering", ["lattice", "random"])
+def test_filter_row_orders(case, numbering, tile_rows, monkeypatch):
+    """The row tiles in the given numbering and in graph-locality order (and
+    the automatic choice) give the same bits, and match the oracle; a random
+    numbering exercises tiles of rows far apart in memory."""
+    banner(f"apply_filter row orders, {numbering} numbering, tile_rows={tile_rows}")
+    monkeypatch.setenv("PFEIG_TILE_ROWS", tile_rows)
+    g = case.g if numbering == "lattice" else relabel(case.g, 4)
+    H = case.H if numbering == "lattice" else hessian.glass_H(g)[0]
+    f = design(case, 25)
+    X = gaussian_block(case.n, 96, 77)
+    out = {}
+    for mode in ["0", "1", None]:
+        if mode is None:
+            monkeypatch.delenv("PFEIG_ROW_ORDER", raising=False)
+        else:
+            monkeypatch.setenv("PFEIG_ROW_ORDER", mode)
+        h = P.pfe_create(0)
+        try:
+            P.pfe_set_hessian(h, g.row_ptr, g.col_idx, g.blocks, g.masses)
+            P.pfe_set_bounds(h, 0.0, case.ub)
+            out[mode] = (P.pfe_apply_filter(h, f, X), P.pfe_apply_filter(h, f, X.astype(np.float32)))
+        finally:
+            P.pfe_destroy(h)
+    ref = chebyshev.apply_filter(H, f.c, f.e, f.coef, X)
+    assert rel_err(out["0"][0], ref) < 1e-12
+    assert rel_err(out["0"][1], ref) < 5e-5
+    for mode in ["1", None]:
+        np.testing.assert_array_equal(out[mode][0], out["0"][0])
+        np.testing.assert_array_equal(out[mode][1], out["0"][1])

@@ -36,3 +36,30 @@ def test_gaussian_block_seeded():
     assert a.flags["C_CONTIGUOUS"] and a.shape == (50, 4)
     assert np.array_equal(a, gaussian_block(50, 4, 11))
     assert not np.array_equal(a, gaussian_block(50, 4, 12))
+
+
+def test_relabel_is_the_same_network():
+    """Renumbered glass: every block moves with its atoms, K'(a, b) = K(perm a, perm b)."""
+    from synth import relabel
+    g = lattice_glass(216, seed=3)
+    r = relabel(g, 9)
+    perm = np.random.Generator(np.random.PCG64(9)).permutation(g.n_atoms)
+    def dense(x):
+        K = np.zeros((x.n, x.n))
+        for i in range(x.n_atoms):
+            for k in range(x.row_ptr[i], x.row_ptr[i + 1]):
+                j = x.col_idx[k]
+                K[3 * i:3 * i + 3, 3 * j:3 * j + 3] = x.blocks[k]
+        return K
+    p3 = (3 * perm[:, None] + np.arange(3)).ravel()
+    # off-diagonal blocks move exactly; a diagonal block is a sum whose order
+    # follows the numbering, so it agrees to rounding
+    D0, D1 = dense(g)[np.ix_(p3, p3)], dense(r)
+    np.testing.assert_allclose(D1, D0, rtol=0, atol=1e-14 * np.abs(D0).max())
+    off = ~np.kron(np.eye(g.n_atoms, dtype=bool), np.ones((3, 3), dtype=bool))
+    np.testing.assert_array_equal(D1[off], D0[off])
+    np.testing.assert_array_equal(r.masses, g.masses[perm])
+    assert np.all(r.pairs[:, 0] < r.pairs[:, 1])
+    assert np.all(np.diff(r.pairs[:, 0]) >= 0)
+    # the numbering is scrambled: most springs join atoms far apart in it
+    assert np.median(np.abs(r.pairs[:, 1] - r.pairs[:, 0])) > g.n_atoms / 8

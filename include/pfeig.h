@@ -66,7 +66,9 @@ typedef enum {
 #define PFE_FP32 1   /* FP32 block values and vectors, FP32 accumulation */
 
 /* Create a handle on HIP device `device`.  `hip_stream` is a hipStream_t to
- * run on (NULL: the library creates its own stream).  The stream must have the
+ * run on (NULL: the library creates its own blocking stream, ordered against
+ * the legacy default stream, so device arrays written there before the call
+ * are complete when the library reads them).  The stream must have the
  * default priority. */
 pfe_status pfe_create(int device, void* hip_stream, pfe_handle* out);
 void pfe_destroy(pfe_handle h);

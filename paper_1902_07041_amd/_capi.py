@@ -191,7 +191,10 @@ def pfe_version() -> str:
 
 def pfe_create(device: int = 0, stream=None):
     """Handle on `device`.  stream: a hipStream_t as int, or None for torch's
-    current stream on that device (the library's own stream if torch has none)."""
+    current stream on that device.  Torch's default stream (handle 0) is not
+    passed: the library then runs on its own blocking stream, which is ordered
+    against the legacy default stream, so tensors torch is still writing there
+    are complete before the library reads them."""
     L = load_library()
     if stream is None:
         try:

@@ -426,8 +426,11 @@ pfe_status pfe_create(int device, void* hip_stream, pfe_handle* out) {
   if (hip_stream) {
     h->stream = static_cast<hipStream_t>(hip_stream);
   } else {
-    if ((e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking)) != hipSuccess)
-      return create_fail(h, PFE_EHIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+    // a blocking stream: work on it is ordered against the legacy default
+    // stream, where a caller (torch's default stream included) may still be
+    // writing the device arrays it passes
+    if ((e = hipStreamCreate(&h->stream)) != hipSuccess)
+      return create_fail(h, PFE_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     h->own_stream = true;
   }
   if ((e = hipEventCreate(&h->ev[0])) != hipSuccess || (e = hipEventCreate(&h->ev[1])) != hipSuccess ||

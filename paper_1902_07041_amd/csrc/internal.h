@@ -80,7 +80,7 @@ struct Bsr {
   // [tile_ptr[t], tile_ptr[t+1]) of tile_cm, each a (column, row mask) pair
   // (bit r set when row tile_row[t*R + r] stores a block in that column),
   // sorted by column.  With tiles active the fused step reads its block
-  // values in tile order: the blocks of tile t start at tile_vptr[t] and
+  // values in tile order: the blocks of tile t are [tile_vptr[t], tile_vptr[t+1]) and
   // follow (union column, tile row) order.  tile_cm carries kBsrPad padded
   // entries.
   int tile_rows = 0;

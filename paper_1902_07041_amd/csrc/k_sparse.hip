@@ -77,6 +77,22 @@ __device__ __forceinline__ void step_epilogue(typename VT<T, VW>::type (&acc)[3]
                                               const T* add, T* out, int64_t ld, T alpha, T beta,
                                               T delta, T zeta) {
   using vt = typename VT<T, VW>::type;
+  // All loads of the row are issued before its first store: out may alias
+  // prev or add (element by element), so no load may follow a store, and
+  // issuing them together costs one memory round trip instead of three.
+  vt b[3][NP], d[3][NP], z[3][NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    if (!act[p]) continue;
+    const int c = (lane + 64 * p) * VW;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int64_t off = (int64_t)(3 * row + a) * ld + col0 + c;
+      b[a][p] = beta != T(0) ? *reinterpret_cast<const vt*>(tin + off) : vt(0);
+      d[a][p] = delta != T(0) ? ld_nt(reinterpret_cast<const vt*>(prev + off)) : vt(0);
+      z[a][p] = zeta != T(0) ? ld_nt(reinterpret_cast<const vt*>(add + off)) : vt(0);
+    }
+  }
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     if (!act[p]) continue;
@@ -85,9 +101,9 @@ __device__ __forceinline__ void step_epilogue(typename VT<T, VW>::type (&acc)[3]
     for (int a = 0; a < 3; ++a) {
       const int64_t off = (int64_t)(3 * row + a) * ld + col0 + c;
       vt o = alpha * acc[a][p];
-      if (beta != T(0)) o += beta * *reinterpret_cast<const vt*>(tin + off);
-      if (delta != T(0)) o += delta * ld_nt(reinterpret_cast<const vt*>(prev + off));
-      if (zeta != T(0)) o += zeta * ld_nt(reinterpret_cast<const vt*>(add + off));
+      o += beta * b[a][p];
+      o += delta * d[a][p];
+      o += zeta * z[a][p];
       if (PFE_CHEB_NT_OUT)
         st_nt(o, reinterpret_cast<vt*>(out + off));
       else
@@ -276,6 +292,10 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
   const int col0 = blockIdx.y * (64 * NP * VW);
   vt acc[R][3][NP];
   bool act[NP];
+  // byte offsets of this lane's columns in the three rows of an atom, so a
+  // gather is one uniform row address plus these (lanes past q read column
+  // col0 of the same rows; their sums are never stored)
+  uint32_t boff[3][NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
 #pragma unroll
@@ -284,60 +304,75 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
       acc[r][1][p] = vt(0);
       acc[r][2][p] = vt(0);
     }
-    act[p] = col0 + (lane + 64 * p) * VW < q;
+    const int c = col0 + (lane + 64 * p) * VW;
+    act[p] = c < q;
+    const int64_t e = act[p] ? c : col0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) boff[a][p] = (uint32_t)((a * ld + e) * (int64_t)sizeof(T));
   }
-  const int64_t u0 = tile_ptr[tile];
-  const int64_t u1 = (alpha != T(0)) ? tile_ptr[tile + 1] : u0;
-  int64_t voff = tile_vptr[tile];
+  const int64_t ld3 = 3 * ld;
+  const int64_t ubase = tile_ptr[tile];
+  const int nrec = (alpha != T(0)) ? (int)(tile_ptr[tile + 1] - ubase) : 0;
+  const int2* rec = tile_cm + ubase;
+  const T* hv = vals + tile_vptr[tile] * 9;
   int rows[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) rows[r] = tile_row[tile * R + r];   // -1: no row
-  const int own = rows[0];
-  for (int64_t k = u0; k < u1; k += U) {
-    vt x[U][3][NP];
-    int2 cm[U];
+  // records of the next batch are requested with this batch's block values
+  // (past the tile: the next tile's records or the padding)
+  int2 cm[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) cm[u] = tile_cm[k + u];
+  for (int u = 0; u < U; ++u) cm[u] = rec[u];
+  for (int k = 0; k < nrec; k += U) {
+    vt x[U][3][NP];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const bool valid = (u == 0) || (k + u < u1);
-      const T* src = tin + (int64_t)(3 * (valid ? cm[u].x : own)) * ld + col0;
+      if (u == 0 || k + u < nrec) {
+        const char* rowp = reinterpret_cast<const char*>(tin + (int64_t)(uint32_t)cm[u].x * ld3);
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int c = (lane + 64 * p) * VW;
-        if (act[p] && valid) {
-          x[u][0][p] = *reinterpret_cast<const vt*>(src + c);
-          x[u][1][p] = *reinterpret_cast<const vt*>(src + ld + c);
-          x[u][2][p] = *reinterpret_cast<const vt*>(src + 2 * ld + c);
-        } else {
-          x[u][0][p] = vt(0);
-          x[u][1][p] = vt(0);
-          x[u][2][p] = vt(0);
-        }
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) x[u][a][p] = *reinterpret_cast<const vt*>(rowp + boff[a][p]);
       }
     }
+    int2 cn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cn[u] = rec[k + U + u];
+    __builtin_amdgcn_sched_barrier(0);   // keep the request here, ahead of the products
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (u == 0 || k + u < u1) {
+      if (u == 0 || k + u < nrec) {
         const int m = cm[u].y;
+        // the record's blocks (consecutive, one per set mask bit) are all
+        // requested before the first product
+        T h[R][9];
+        int nb = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           if ((m >> r) & 1) {
-            const T* hv = vals + voff * 9;
-            ++voff;
-            T h[9];
 #pragma unroll
-            for (int t = 0; t < 9; ++t) h[t] = hv[t];
+            for (int t = 0; t < 9; ++t) h[r][t] = hv[9 * nb + t];
+            ++nb;
+          }
+        }
+        hv += 9 * nb;
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-              acc[r][0][p] += h[0] * x[u][0][p] + h[1] * x[u][1][p] + h[2] * x[u][2][p];
-              acc[r][1][p] += h[3] * x[u][0][p] + h[4] * x[u][1][p] + h[5] * x[u][2][p];
-              acc[r][2][p] += h[6] * x[u][0][p] + h[7] * x[u][1][p] + h[8] * x[u][2][p];
-            }
+        for (int r = 0; r < R; ++r) {
+          if ((m >> r) & 1) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                acc[r][a][p] += h[r][3 * a] * x[u][0][p];
+                acc[r][a][p] += h[r][3 * a + 1] * x[u][1][p];
+                acc[r][a][p] += h[r][3 * a + 2] * x[u][2][p];
+              }
           }
         }
       }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) cm[u] = cn[u];
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -377,6 +412,7 @@ hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev,
                        T* out, int q, int64_t ld, T alpha, T beta, T delta, T zeta,
                        hipStream_t s) {
   const int R = (A.tile_rows >= 2 && A.tile_ptr) ? A.tile_rows : 1;   // vals in tile order
+  if (R >= 2 && (3 * ld) * (int64_t)sizeof(T) > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
   const int64_t units = (R >= 2) ? A.n_tiles : A.n_atoms;   // one wave per unit
   const int64_t nblk = (units + kWavesPerBlock - 1) / kWavesPerBlock;
   const int64_t per_xcd = (nblk + 7) / 8;
@@ -632,7 +668,7 @@ void build_row_tiles(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col
                      std::vector<int32_t>& tile_row, std::vector<int64_t>& perm) {
   const int64_t n_tiles = (n_atoms + R - 1) / R;
   tile_ptr.assign(n_tiles + 1, 0);
-  tile_vptr.assign(n_tiles, 0);
+  tile_vptr.assign(n_tiles + 1, 0);
   tile_row.assign(n_tiles * R, -1);
   tile_cm.clear();
   perm.clear();
@@ -662,6 +698,7 @@ void build_row_tiles(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col
     }
     tile_ptr[t + 1] = tile_ptr[t] + nu;
   }
+  tile_vptr[n_tiles] = (int64_t)perm.size();
   for (int64_t p = 0; p < kBsrPad; ++p) {
     tile_cm.push_back(0);
     tile_cm.push_back(0);

@@ -169,3 +169,27 @@ def test_filter_row_orders(case, numbering, tile_rows, monkeypatch):
     for mode in ["1", None]:
         np.testing.assert_array_equal(out[mode][0], out["0"][0])
         np.testing.assert_array_equal(out[mode][1], out["0"][1])
+
+
+def test_device_inputs_ordered_after_torch_default_stream(case):
+    """A block that torch is still computing on its default stream when the
+    call is made is read complete: the handle's stream is ordered against it."""
+    import torch
+    banner("apply_filter on a device block still being written by torch")
+    f = design(case, 25)
+    h = P.pfe_create(0)
+    try:
+        P.pfe_set_hessian(h, case.g.row_ptr, case.g.col_idx, case.g.blocks, case.g.masses)
+        P.pfe_set_bounds(h, 0.0, case.ub)
+        for trial in range(3):
+            torch.cuda.synchronize()
+            X = torch.full((case.n, 64), 0.5, dtype=torch.float64, device="cuda")
+            for i in range(200):          # a queue of kernels that X depends on
+                X = X + 1e-3 * torch.sin(X + i)
+            Y = torch.empty_like(X)
+            P.pfe_apply_filter(h, f, X, Y)     # enqueued while torch is busy
+            torch.cuda.synchronize()
+            ref = P.pfe_apply_filter(h, f, X.cpu().numpy())
+            np.testing.assert_array_equal(Y.cpu().numpy(), ref)
+    finally:
+        P.pfe_destroy(h)

@@ -38,6 +38,7 @@ struct pfe_ctx {
   int tiled_R = 0;
   bool tiled_local = false;   // rows in locality order
   int tiled_mode = -1;        // order requested when the tiles were built
+  int64_t tiled_span = 0;     // neighbour_span of the pattern
   double h32_c = NAN, h32_e = NAN;
   // bounds
   bool has_bounds = false;
@@ -65,6 +66,7 @@ struct pfe_ctx {
     a.tile_cm = tile_cm.as<int2>();
     a.tile_row = tile_row.as<int32_t>();
     a.tile_local = tiled_local;
+    a.span = tiled_span;
     return a;
   }
   // Block values as the fused step reads them (tile order when tiles are on).
@@ -597,6 +599,7 @@ static Err set_hessian_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const i
       h->tiled_R = R;
       h->tiled_local = local;
       h->tiled_mode = order_mode;
+      h->tiled_span = local ? 0 : pfe::neighbour_span(n_atoms, h->tiled_rp.data(), h->tiled_ci.data());
     }
     PFE_HIP(h->Ht.ensure((size_t)(nnzb + pfe::kBsrPad) * 9 * sizeof(double)));
     PFE_HIP(pfe::zero_f64(h->Ht.as<double>(), (nnzb + pfe::kBsrPad) * 9, h->stream));

@@ -90,6 +90,7 @@ struct Bsr {
   const int2* tile_cm = nullptr;
   const int32_t* tile_row = nullptr;
   bool tile_local = false;   // tile_row follows the locality order (one row range per XCD)
+  int64_t span = 0;          // typical long neighbour offset in rows (natural order)
 };
 
 // Processing order of the atom rows in which contiguous ranges are compact in
@@ -98,6 +99,9 @@ struct Bsr {
 // groups of R rows sharing many block columns.
 void locality_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int leaf, int R,
                     std::vector<int32_t>& order);
+// 90th percentile of the row offsets |i - j| of the off-diagonal blocks,
+// leaving out offsets above n/2 (periodic wrap-around); 0 without any.
+int64_t neighbour_span(int64_t n, const int64_t* row_ptr, const int32_t* col_idx);
 // Fraction of the off-diagonal blocks (i, j) whose rows lie more than
 // `window` positions apart in the processing order `order` (nullptr: natural).
 double far_block_fraction(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,

@@ -98,6 +98,8 @@ __global__ __launch_bounds__(256) void k_sddmm_seg(int n_atoms, const int64_t* _
     double g[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) g[e] = 0.0;
+    // several pairs' loads in flight at once (the pair loop is latency-bound)
+#pragma unroll 4
     for (int mm = 0; mm < m; ++mm) {
       const double wm = w[mm];
       const double* am = A + mm * a_stride;

@@ -218,6 +218,65 @@ __global__ __launch_bounds__(1024) void k_chol_inv(int q, const double* __restri
   if (tid == 0) info[0] = 0;
 }
 
+// LDS-resident variant for q <= kCholLdsMax: the factor is built in place
+// in LDS (two barriers per column: scale row k, then the trailing update),
+// then inverted in place column by column from Z R = I:
+// Z[0:j, j] = -Z[0:j, 0:j] R[0:j, j] / R[j][j], whose j dot products run on
+// 8 threads each, so no step waits on a serial substitution chain.
+constexpr int kCholLdsMax = 128;
+
+__global__ __launch_bounds__(1024) void k_chol_inv_lds(int q, const double* __restrict__ G,
+                                                       double shift, double* __restrict__ Rout,
+                                                       int* info, double* diag_max) {
+  __shared__ double R[kCholLdsMax * kCholLdsMax];
+  __shared__ double col[kCholLdsMax];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0 && diag_max) {
+    double mx = 0.0;
+    for (int i = 0; i < q; ++i) mx = fmax(mx, G[i * q + i]);
+    diag_max[0] = mx;
+  }
+  for (int idx = tid; idx < q * q; idx += nt) {
+    const int i = idx / q, j = idx - i * q;
+    R[idx] = (j >= i) ? G[idx] + (i == j ? shift : 0.0) : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < q; ++k) {
+    const double d = R[k * q + k];   // the same value in every thread
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (tid == 0) info[0] = k + 1;
+      return;
+    }
+    const double rkk = sqrt(d);
+    for (int j = k + 1 + tid; j < q; j += nt) R[k * q + j] /= rkk;
+    __syncthreads();
+    if (tid == 0) R[k * q + k] = rkk;
+    for (int i = k + 1 + (tid >> 5); i < q; i += (nt >> 5)) {
+      const double rki = R[k * q + i];
+      for (int j = i + (tid & 31); j < q; j += 32) R[i * q + j] -= rki * R[k * q + j];
+    }
+    __syncthreads();
+  }
+  const int ri = tid >> 3, rl = tid & 7;   // 8 threads per row of Z
+  for (int j = 0; j < q; ++j) {
+    if (tid < j) col[tid] = R[tid * q + j];
+    __syncthreads();
+    const double zjj = 1.0 / R[j * q + j];
+    double sum = 0.0;
+    if (ri < j)
+      for (int k = ri + rl; k < j; k += 8) sum += R[ri * q + k] * col[k];
+    sum += __shfl_xor(sum, 1);
+    sum += __shfl_xor(sum, 2);
+    sum += __shfl_xor(sum, 4);
+    __syncthreads();
+    if (rl == 0 && ri < j) R[ri * q + j] = -zjj * sum;
+    if (tid == 0) R[j * q + j] = zjj;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < q * q; idx += nt) Rout[idx] = R[idx];
+  if (tid == 0) info[0] = 0;
+}
+
 // ------------------------------------------------------- Jacobi eigensolve
 // One work-group, A and V in global scratch.  Round-robin (circle method)
 // ordering: m/2 disjoint rotations per step, m-1 steps per sweep.  A
@@ -764,6 +823,11 @@ hipError_t chol_inv_f64(int q, const double* G, double shift, double* Rinv, int*
                         double* diag_max, hipStream_t s) {
   // Rinv doubles as R during the factorisation; the inverse is built in the
   // second half of the same allocation (caller provides 2 q^2 doubles).
+  if (q <= kCholLdsMax) {
+    hipLaunchKernelGGL(k_chol_inv_lds, dim3(1), dim3(1024), 0, s, q, G, shift, Rinv, info,
+                       diag_max);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, s, q, G, shift, Rinv, Rinv + (int64_t)q * q,
                      info, diag_max);
   return hipGetLastError();

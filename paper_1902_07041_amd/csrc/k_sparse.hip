@@ -416,11 +416,20 @@ hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev,
   const int64_t units = (R >= 2) ? A.n_tiles : A.n_atoms;   // one wave per unit
   const int64_t nblk = (units + kWavesPerBlock - 1) / kWavesPerBlock;
   const int64_t per_xcd = (nblk + 7) / 8;
-  // rows in locality order: one contiguous range (a compact region) per XCD;
-  // natural order: chunks of PFE_CHEB_CHUNK work-groups dealt round-robin
+  // Rows in locality order: one contiguous range (a compact region) per XCD.
+  // Natural order: chunks dealt round-robin, 8 chunks spanning the pattern's
+  // typical long neighbour offset, so a row and its neighbour one "plane"
+  // away fall on the same XCD and the second gather hits that XCD's L2 (1e6-
+  // atom lattice glass: 2870 us per step against 3265 us with fixed 256-row
+  // chunks; no change at 1e5 atoms, where 8 such chunks already span one
+  // plane within 7 %); PFE_CHEB_CHUNK work-groups when the pattern gives none.
   int chunk = (R >= 2 && A.tile_local) ? 0 : PFE_CHEB_CHUNK;
-  if (chunk_override() >= 0) chunk = chunk_override();
   if (R >= 2) chunk = std::max(chunk > 0 ? 1 : 0, chunk / R);   // keep rows per chunk comparable
+  if (R >= 2 && !A.tile_local && A.span > 0) {
+    const int64_t rows_per_group = (int64_t)kWavesPerBlock * R;
+    chunk = (int)std::max<int64_t>(1, (A.span + 4 * rows_per_group) / (8 * rows_per_group));
+  }
+  if (chunk_override() >= 0) chunk = chunk_override();         // work-groups, as given
   if (chunk <= 0 || chunk > per_xcd) chunk = (int)per_xcd;
   const int64_t grid_x = ((nblk + 8LL * chunk - 1) / (8LL * chunk)) * 8LL * chunk;
   const int cols_per_group = 64 * NP * VW;

@@ -175,4 +175,18 @@ double far_block_fraction(int64_t n, const int64_t* row_ptr, const int32_t* col_
   return off > 0 ? (double)far / (double)off : 0.0;
 }
 
+int64_t neighbour_span(int64_t n, const int64_t* row_ptr, const int32_t* col_idx) {
+  // every 16th block row is enough for a percentile
+  std::vector<int64_t> off;
+  for (int64_t i = 0; i < n; i += 16)
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      const int64_t d = std::abs((int64_t)col_idx[k] - i);
+      if (d > 0 && 2 * d <= n) off.push_back(d);
+    }
+  if (off.empty()) return 0;
+  const size_t at = (off.size() * 9) / 10;
+  std::nth_element(off.begin(), off.begin() + at, off.end());
+  return off[at];
+}
+
 }  // namespace pfe

@@ -83,16 +83,117 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int q1, int q2,
       }
 }
 
-__global__ void k_gram_reduce(int nsplit, int64_t count, const double* __restrict__ work,
-                              double* __restrict__ G) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
+// G = sum over splits of the partial tiles, in a fixed order: 16 outputs per
+// work-group, 16 threads per output each summing every sixteenth split, then
+// the sixteen sums in thread order.
+__global__ __launch_bounds__(256) void k_gram_reduce(int nsplit, int64_t count,
+                                                     const double* __restrict__ work,
+                                                     double* __restrict__ G) {
+  __shared__ double part[16][17];
+  const int o = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + o;
   double s = 0.0;
-  for (int p = 0; p < nsplit; ++p) s += work[(int64_t)p * count + i];
-  G[i] = s;
+  if (i < count)
+    for (int p = grp; p < nsplit; p += 16) s += work[(int64_t)p * count + i];
+  part[grp][o] = s;
+  __syncthreads();
+  if (grp == 0 && i < count) {
+    double t = part[0][o];
+    for (int g = 1; g < 16; ++g) t += part[g][o];
+    G[i] = t;
+  }
 }
 
+// Small Gram (q1, q2 <= 128): one work-group forms the whole q1 x q2 product
+// of its row range, so nothing is padded beyond a multiple of 32.  Waves are
+// 2 x 2, each owning MT x NT MFMA tiles of 16 x 16; rows are staged 16 at a
+// time through LDS and the next 16 are loaded into registers while the
+// current ones multiply.
+constexpr int kGramSmallRows = 16;
+
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void k_gram_small(int64_t n, int q1, int q2,
+                                                    const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ B, int64_t ldb,
+                                                    int64_t rows_per_split,
+                                                    double* __restrict__ work) {
+  constexpr int Q1 = 32 * MT, Q2 = 32 * NT;
+  constexpr int LA = (kGramSmallRows * Q1) / 256, LB = (kGramSmallRows * Q2) / 256;
+  __shared__ double sA[kGramSmallRows][Q1 + 1];
+  __shared__ double sB[kGramSmallRows][Q2 + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 16 * MT, wn = (wave & 1) * 16 * NT;
+  const int64_t r_begin = (int64_t)blockIdx.x * rows_per_split;
+  const int64_t r_end = min(n, r_begin + rows_per_split);
+  d4 acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = d4(0.0);
+  double ra[LA], rb[LB];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int t = 0; t < LA; ++t) {
+      const int idx = tid + 256 * t, rr = idx / Q1, c = idx % Q1;
+      const int64_t r = r0 + rr;
+      ra[t] = (r < r_end && c < q1) ? A[r * lda + c] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < LB; ++t) {
+      const int idx = tid + 256 * t, rr = idx / Q2, c = idx % Q2;
+      const int64_t r = r0 + rr;
+      rb[t] = (r < r_end && c < q2) ? B[r * ldb + c] : 0.0;
+    }
+  };
+  if (r_begin < r_end) fetch(r_begin);
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGramSmallRows) {
+#pragma unroll
+    for (int t = 0; t < LA; ++t) {
+      const int idx = tid + 256 * t;
+      sA[idx / Q1][idx % Q1] = ra[t];
+    }
+#pragma unroll
+    for (int t = 0; t < LB; ++t) {
+      const int idx = tid + 256 * t;
+      sB[idx / Q2][idx % Q2] = rb[t];
+    }
+    __syncthreads();
+    if (r0 + kGramSmallRows < r_end) fetch(r0 + kGramSmallRows);
+#pragma unroll
+    for (int kk = 0; kk < kGramSmallRows; kk += 4) {
+      const int k = kk + (lane >> 4);
+      double a[MT], b[NT];
+#pragma unroll
+      for (int i = 0; i < MT; ++i) a[i] = sA[k][wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) b[j] = sB[k][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = mfma16x16x4(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  double* out = work + (int64_t)blockIdx.x * q1 * q2;
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wm + 16 * i + (lane >> 4) + 4 * r;
+        const int col = wn + 16 * j + (lane & 15);
+        if (row < q1 && col < q2) out[(int64_t)row * q2 + col] = acc[i][j][r];
+      }
+}
+
+constexpr int kGramSmallMax = 128;
+
 int gram_splits(int64_t n, int q1, int q2) {
+  if (q1 <= kGramSmallMax && q2 <= kGramSmallMax) {
+    int64_t want = std::min<int64_t>(512, (n + 255) / 256);   // two work-groups per CU
+    return (int)std::max<int64_t>(want, 1);
+  }
   const int tiles = ((q1 + 63) / 64) * ((q2 + 63) / 64);
   int64_t want = 1024 / tiles;                     // ~1024 work-groups in total
   if (want < 8) want = 8;
@@ -151,6 +252,76 @@ __global__ __launch_bounds__(256) void k_gemm_tall(int64_t n, int q1, int q2,
 #pragma unroll
         for (int t = 0; t < kTiles; ++t)
           if (cc[t] < q2) C[row * ldc + cc[t]] = acc[t][r];
+      }
+    }
+  }
+}
+
+// Tall GEMM for q1, q2 <= 128: Bm (padded to KM x 16 NT) is staged once per
+// work-group in LDS; each wave then walks 16-row tiles of A with NT
+// independent 16 x 16 accumulators, its A fragments loaded straight from
+// memory one tile ahead.  A wave reads all of a tile's rows before writing
+// them, so C may overwrite A.
+template <int KM, int NT>
+__global__ __launch_bounds__(256) void k_gemm_bres(int64_t n, int q1, int q2, const double* A,
+                                                   int64_t lda, const double* __restrict__ Bm,
+                                                   double* C, int64_t ldc) {
+  constexpr int Q2 = 16 * NT, LDB = Q2 + 1;
+  __shared__ double sB[KM * LDB];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < KM * Q2; idx += 256) {
+    const int k = idx / Q2, c = idx % Q2;
+    sB[k * LDB + c] = (k < q1 && c < q2) ? Bm[(int64_t)k * q2 + c] : 0.0;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  const int64_t ntile = (n + 15) / 16;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  constexpr int KT = KM / 4;
+  // A fragments of one tile: lane l holds A[r0 + l % 16][4 kb + l / 16]
+  auto load = [&](double (&f)[KT], int64_t t) {
+    const int64_t r0 = t * 16, r = r0 + (lane & 15);
+    const bool rok = r < n;
+    const double* arow = A + (rok ? r : r0) * lda;
+#pragma unroll
+    for (int kb = 0; kb < KT; ++kb) {
+      const int k = 4 * kb + (lane >> 4);
+      f[kb] = (rok && k < q1) ? arow[k] : 0.0;
+    }
+  };
+  double fn[KT];
+  int64_t t = (int64_t)blockIdx.x * 4 + wave;
+  if (t < ntile) load(fn, t);
+  for (; t < ntile; t += stride) {
+    double fc[KT];
+#pragma unroll
+    for (int kb = 0; kb < KT; ++kb) fc[kb] = fn[kb];
+    // the next tile's fragments are in flight during this tile's products;
+    // its rows differ from this tile's, so C overwriting A stays safe
+    if (t + stride < ntile) load(fn, t + stride);
+    d4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = d4(0.0);
+#pragma unroll
+    for (int kb = 0; kb < KT; ++kb) {
+      const int k = 4 * kb + (lane >> 4);
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+        acc[j] = mfma16x16x4(fc[kb], sB[k * LDB + 16 * j + (lane & 15)], acc[j]);
+      // one k-step's B reads at a time (the MFMAs in flight cover their
+      // latency); hoisting them all would cost KT x NT registers
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const int64_t r0 = t * 16;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int64_t row = r0 + (lane >> 4) + 4 * rr;
+      if (row < n) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const int col = 16 * j + (lane & 15);
+          if (col < q2) C[row * ldc + col] = acc[j][rr];
+        }
       }
     }
   }
@@ -506,57 +677,65 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int q, const double* __rest
 }
 
 // ------------------------------------------------------- column reductions
-constexpr int kColRows = 512;   // rows per partial block
+constexpr int kColRows = 128;   // rows per partial block
 
-__global__ __launch_bounds__(64) void k_col_partial(int64_t n, int q, const double* __restrict__ W,
-                                                    const double* __restrict__ X, int64_t ld,
-                                                    const double* __restrict__ theta,
-                                                    double* __restrict__ part) {
+// Column partials over kColRows rows: lanes take columns (64 per pass), the
+// four waves every fourth row, summed across waves in wave order.  MODE 0:
+// sum (W - theta X)^2 (X may be null); MODE 1: sum X * Y (W holds X).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_col_partial(int64_t n, int q, const double* __restrict__ W,
+                                                     const double* __restrict__ X, int64_t ld,
+                                                     const double* __restrict__ theta,
+                                                     double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * kColRows;
-  int64_t r1 = r0 + kColRows;
-  if (r1 > n) r1 = n;
-  for (int j = threadIdx.x; j < q; j += 64) {
-    const double th = theta ? theta[j] : 0.0;
+  const int64_t r1 = min(n, r0 + kColRows);
+  for (int j0 = 0; j0 < q; j0 += 64) {
+    const int j = j0 + lane;
     double s = 0.0;
-    for (int64_t r = r0; r < r1; ++r) {
-      double v = W[r * ld + j];
-      if (X) v -= th * X[r * ld + j];
-      s += v * v;
+    if (j < q) {
+      const double th = (MODE == 0 && theta) ? theta[j] : 0.0;
+#pragma unroll 4
+      for (int64_t r = r0 + wave; r < r1; r += 4) {
+        if (MODE == 0) {
+          double v = W[r * ld + j];
+          if (X) v -= th * X[r * ld + j];
+          s += v * v;
+        } else {
+          s += W[r * ld + j] * X[r * ld + j];
+        }
+      }
     }
-    part[(int64_t)blockIdx.x * q + j] = s;
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && j < q)
+      part[(int64_t)blockIdx.x * q + j] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    __syncthreads();
   }
 }
 
-__global__ void k_col_final(int nblk, int q, const double* __restrict__ part, double scale,
-                            double* __restrict__ res) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= q) return;
+// res[j] = f(sum over blocks of part[b][j]): 16 columns per work-group, 16
+// threads per column summing every sixteenth block, then in thread order.
+// f = scale * sqrt (norms) or the identity (dots).
+template <bool SQRT>
+__global__ __launch_bounds__(256) void k_col_final(int nblk, int q, const double* __restrict__ part,
+                                                   double scale, double* __restrict__ res) {
+  __shared__ double acc[16][17];
+  const int o = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int j = blockIdx.x * 16 + o;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * q + j];
-  res[j] = sqrt(s) * scale;
-}
-
-__global__ __launch_bounds__(64) void k_coldot_partial(int64_t n, int q,
-                                                       const double* __restrict__ X,
-                                                       const double* __restrict__ Y, int64_t ld,
-                                                       double* __restrict__ part) {
-  const int64_t r0 = (int64_t)blockIdx.x * kColRows;
-  int64_t r1 = r0 + kColRows;
-  if (r1 > n) r1 = n;
-  for (int j = threadIdx.x; j < q; j += 64) {
-    double s = 0.0;
-    for (int64_t r = r0; r < r1; ++r) s += X[r * ld + j] * Y[r * ld + j];
-    part[(int64_t)blockIdx.x * q + j] = s;
+  if (j < q)
+    for (int b = grp; b < nblk; b += 16) s += part[(int64_t)b * q + j];
+  acc[grp][o] = s;
+  __syncthreads();
+  if (grp == 0 && j < q) {
+    double t = acc[0][o];
+    for (int g = 1; g < 16; ++g) t += acc[g][o];
+    res[j] = SQRT ? sqrt(t) * scale : t;
   }
 }
-__global__ void k_colsum_final(int nblk, int q, const double* __restrict__ part,
-                               double* __restrict__ res) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= q) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * q + j];
-  res[j] = s;
-}
+
 __global__ void k_col_scale_inv(int64_t n, int q, double* __restrict__ X, int64_t ld,
                                 const double* __restrict__ nrm) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -792,13 +971,26 @@ hipError_t gram_f64(int64_t n, int q1, int q2, const double* A, int64_t lda, con
   if (q1 == 0 || q2 == 0) return hipSuccess;
   const int nsplit = gram_splits(n, q1, q2);
   int64_t rows = (n + nsplit - 1) / nsplit;
-  rows = ((rows + kGramRows - 1) / kGramRows) * kGramRows;
-  const int tiles = ((q1 + 63) / 64) * ((q2 + 63) / 64);
+  rows = ((rows + kGramSmallRows - 1) / kGramSmallRows) * kGramSmallRows;
   double* w = static_cast<double*>(work);
-  hipLaunchKernelGGL(k_gram_partial, dim3(nsplit, tiles), dim3(256), 0, s, n, q1, q2, A, lda, B,
-                     ldb, rows, w);
+  if (q1 <= kGramSmallMax && q2 <= kGramSmallMax) {
+    const int mt = (q1 + 31) / 32, nt = (q2 + 31) / 32;
+#define PFE_GRAM_CASE(M_, N_)                                                                  \
+    if (mt == M_ && nt == N_)                                                                  \
+      hipLaunchKernelGGL((k_gram_small<M_, N_>), dim3(nsplit), dim3(256), 0, s, n, q1, q2, A,   \
+                         lda, B, ldb, rows, w);
+    PFE_GRAM_CASE(1, 1) PFE_GRAM_CASE(1, 2) PFE_GRAM_CASE(1, 3) PFE_GRAM_CASE(1, 4)
+    PFE_GRAM_CASE(2, 1) PFE_GRAM_CASE(2, 2) PFE_GRAM_CASE(2, 3) PFE_GRAM_CASE(2, 4)
+    PFE_GRAM_CASE(3, 1) PFE_GRAM_CASE(3, 2) PFE_GRAM_CASE(3, 3) PFE_GRAM_CASE(3, 4)
+    PFE_GRAM_CASE(4, 1) PFE_GRAM_CASE(4, 2) PFE_GRAM_CASE(4, 3) PFE_GRAM_CASE(4, 4)
+#undef PFE_GRAM_CASE
+  } else {
+    const int tiles = ((q1 + 63) / 64) * ((q2 + 63) / 64);
+    hipLaunchKernelGGL(k_gram_partial, dim3(nsplit, tiles), dim3(256), 0, s, n, q1, q2, A, lda,
+                       B, ldb, rows, w);
+  }
   const int64_t count = (int64_t)q1 * q2;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks(count, 256)), dim3(256), 0, s, nsplit, count, w,
+  hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks(count, 16)), dim3(256), 0, s, nsplit, count, w,
                      G);
   return hipGetLastError();
 }
@@ -806,6 +998,24 @@ hipError_t gram_f64(int64_t n, int q1, int q2, const double* A, int64_t lda, con
 hipError_t gemm_tall_f64(int64_t n, int q1, int q2, const double* A, int64_t lda,
                          const double* Bm, double* C, int64_t ldc, hipStream_t s) {
   if (n == 0 || q2 == 0) return hipSuccess;
+  if (q1 <= 128 && q2 <= 128) {
+    const int km = (q1 + 31) / 32, nt = (q2 + 15) / 16;
+    const int64_t tiles = (n + 15) / 16;
+    // two work-groups per CU when Bm fits twice in the 160 KB of LDS
+    const int per_cu = (km * 32 * (16 * nt + 1) * 8 <= 80 * 1024) ? 2 : 1;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 256 * per_cu));
+#define PFE_GEMM_CASE(K_, N_)                                                                \
+    if (km == K_ && nt == N_) {                                                              \
+      hipLaunchKernelGGL((k_gemm_bres<32 * K_, N_>), dim3(grid), dim3(256), 0, s, n, q1, q2, \
+                         A, lda, Bm, C, ldc);                                                \
+      return hipGetLastError();                                                              \
+    }
+#define PFE_GEMM_ROW(K_) PFE_GEMM_CASE(K_, 1) PFE_GEMM_CASE(K_, 2) PFE_GEMM_CASE(K_, 3) \
+    PFE_GEMM_CASE(K_, 4) PFE_GEMM_CASE(K_, 5) PFE_GEMM_CASE(K_, 6) PFE_GEMM_CASE(K_, 7) PFE_GEMM_CASE(K_, 8)
+    PFE_GEMM_ROW(1) PFE_GEMM_ROW(2) PFE_GEMM_ROW(3) PFE_GEMM_ROW(4)
+#undef PFE_GEMM_ROW
+#undef PFE_GEMM_CASE
+  }
   const int q1p = ((q1 + 3) / 4) * 4 + 1;
   if ((size_t)32 * q1p * sizeof(double) <= 65536) {
     hipLaunchKernelGGL(k_gemm_tall<32>, dim3(nblocks(n, 32)), dim3(256),
@@ -849,16 +1059,17 @@ hipError_t sym_eig_f64(int q, const double* S, double* evals, double* Q, void* w
 }
 
 size_t colnorm_work_bytes(int64_t n, int q) {
-  return (size_t)nblocks(n, kColRows) * q * sizeof(double);
+  return (size_t)std::max(1u, nblocks(n, kColRows)) * q * sizeof(double);
 }
 
 hipError_t resid_norms_f64(int64_t n, int q, const double* W, const double* X, int64_t ld,
                            const double* theta, double inv_scale, double* res, void* work,
                            hipStream_t s) {
-  const unsigned nb = nblocks(n, kColRows);
+  const unsigned nb = std::max(1u, nblocks(n, kColRows));   // n = 0: one zero partial
   double* part = static_cast<double*>(work);
-  hipLaunchKernelGGL(k_col_partial, dim3(nb), dim3(64), 0, s, n, q, W, X, ld, theta, part);
-  hipLaunchKernelGGL(k_col_final, dim3(nblocks(q, 256)), dim3(256), 0, s, (int)nb, q, part,
+  if (q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col_partial<0>, dim3(nb), dim3(256), 0, s, n, q, W, X, ld, theta, part);
+  hipLaunchKernelGGL(k_col_final<true>, dim3(nblocks(q, 16)), dim3(256), 0, s, (int)nb, q, part,
                      inv_scale, res);
   return hipGetLastError();
 }
@@ -870,11 +1081,12 @@ hipError_t col_norms_f64(int64_t n, int q, const double* X, int64_t ld, double* 
 
 hipError_t col_dots_f64(int64_t n, int q, const double* X, const double* Y, int64_t ld,
                         double* res, void* work, hipStream_t s) {
-  const unsigned nb = nblocks(n, kColRows);
+  const unsigned nb = std::max(1u, nblocks(n, kColRows));   // n = 0: one zero partial
   double* part = static_cast<double*>(work);
-  hipLaunchKernelGGL(k_coldot_partial, dim3(nb), dim3(64), 0, s, n, q, X, Y, ld, part);
-  hipLaunchKernelGGL(k_colsum_final, dim3(nblocks(q, 256)), dim3(256), 0, s, (int)nb, q, part,
-                     res);
+  if (q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col_partial<1>, dim3(nb), dim3(256), 0, s, n, q, X, Y, ld, nullptr, part);
+  hipLaunchKernelGGL(k_col_final<false>, dim3(nblocks(q, 16)), dim3(256), 0, s, (int)nb, q, part,
+                     1.0, res);
   return hipGetLastError();
 }
 hipError_t col_scale_inv_f64(int64_t n, int q, double* X, int64_t ld, const double* nrm,

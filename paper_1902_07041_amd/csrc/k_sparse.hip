@@ -399,6 +399,14 @@ __global__ void k_permute_blocks(int64_t nnzb, const int64_t* __restrict__ perm,
 #define PFE_CHEB_CHUNK 64    // work-groups per XCD chunk (measured best on MI355X); 0: one range per XCD
 #endif
 
+int pass_cols_override() {
+  static int v = [] {
+    const char* e = std::getenv("PFEIG_CHEB_PASS_COLS");
+    return e ? std::atoi(e) : 0;
+  }();
+  return v;
+}
+
 int chunk_override() {
   static int v = [] {
     const char* e = std::getenv("PFEIG_CHEB_CHUNK");
@@ -489,7 +497,19 @@ hipError_t dispatch_cheb(const Bsr& A, const T* vals, const T* tin, const T* pre
   int vw = want;
   while (vw > 1 && !fits(vw)) vw /= 2;
   const int chunks = (q + vw - 1) / vw;
-  const int np = chunks <= 64 ? 1 : (chunks <= 128 ? 2 : 4);
+  int np = chunks <= 64 ? 1 : (chunks <= 128 ? 2 : 4);
+  // Columns per pass (blockIdx.y takes the rest).  FP64 beyond 192 columns
+  // runs 128-column passes (VW 2, 8 waves per SIMD) instead of one VW-4 pass
+  // (126 VGPRs, 4 waves): q = 256 on the 1e6-atom glass 8.79 -> 7.58 ms per
+  // step, although the matrix is read once per pass; at q = 160 (a second
+  // pass of 32 columns) and in FP32 one pass measured faster.
+  // PFEIG_CHEB_PASS_COLS overrides.
+  int lim = pass_cols_override();
+  if (lim <= 0 && sizeof(T) == 8 && q > 192) lim = 128;
+  if (lim > 0) {
+    while (np > 1 && 64 * np * vw > lim) np /= 2;
+    while (vw > 1 && 64 * np * vw > lim && fits(vw / 2)) vw /= 2;
+  }
 #define PFE_CHEB_CASE(VW_, NP_)                                                               \
   if (vw == VW_ && np == NP_)                                                                 \
     return launch_cheb<T, VW_, NP_>(A, vals, tin, prev, add, out, q, ld, alpha, beta, delta,  \

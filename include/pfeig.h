@@ -195,8 +195,10 @@ typedef struct {
                           1e-8 (FP32 filter form) */
   int32_t max_iter;    /* outer iterations (filter applications); 0 -> 100 */
   int32_t precision;   /* PFE_FP64, or PFE_FP32: FP32 filter with FP64
-                          orthonormalisation, Rayleigh-Ritz and residuals, then
-                          exactly one FP64 refinement sweep */
+                          orthonormalisation, Rayleigh-Ritz and residuals until
+                          the residuals plateau at the FP32 rounding floor (or
+                          come within 30 tol), then FP64 refinement sweeps until
+                          converged: one when that floor is within reach of tol */
   uint64_t seed;       /* start block seed when x0 == NULL */
   const double* x0;    /* optional start block [n][block] (host, or device with
                           PFE_DEVICE_PTRS in flags) */
@@ -214,7 +216,7 @@ typedef struct {
 typedef struct {
   int32_t iterations;        /* outer iterations in total */
   int32_t fp64_iterations;   /* of which with the FP64 filter */
-  int32_t refined;           /* 1 if the FP64 refinement sweep ran (FP32 form) */
+  int32_t refined;           /* FP64 refinement sweeps run (FP32 form) */
   int32_t degree;
   double eps, c, e, xi, eta;
   int64_t filter_steps;      /* fused Chebyshev step launches */

@@ -97,6 +97,25 @@ Err upload(pfe_handle h, T* dst, const T* src, int64_t count, bool device_ptrs) 
                          h->stream));
   return pfe::ok();
 }
+// Host block [n][q] into device rows of stride ld >= q: one contiguous copy
+// (into `staging` when ld > q, at least n q doubles, which is left zeroed),
+// then the strided placement on the device.  A 2-D copy from pageable host
+// memory moves one row at a time (about 27 s for 3e6 rows of 160 columns).
+Err upload_block(pfe_handle h, double* dst, int64_t ld, const double* src, int q, int64_t n,
+                 double* staging) {
+  if (n == 0 || q == 0) return pfe::ok();
+  if (ld == q) {
+    PFE_HIP(hipMemcpyAsync(dst, src, (size_t)n * q * sizeof(double), hipMemcpyHostToDevice,
+                           h->stream));
+    return pfe::ok();
+  }
+  PFE_HIP(hipMemcpyAsync(staging, src, (size_t)n * q * sizeof(double), hipMemcpyHostToDevice,
+                         h->stream));
+  PFE_HIP(pfe::copy_cols_f64(n, q, staging, q, dst, ld, h->stream));
+  PFE_HIP(pfe::zero_f64(staging, n * q, h->stream));
+  return pfe::ok();
+}
+
 template <typename T>
 Err download(pfe_handle h, T* dst, const T* src, int64_t count, bool device_ptrs) {
   if (count == 0) return pfe::ok();
@@ -126,6 +145,10 @@ constexpr int kDefaultTileRows = PFE_TILE_ROWS;
 constexpr int kOrderLeaf = 256;
 constexpr int64_t kOrderWindow = 32768;
 constexpr double kOrderFarMax = 0.05;
+// Largest residual at which a plateau of the FP32-filter iterations is taken
+// for their rounding floor (and answered by FP64 refinement, not by a higher
+// degree).
+constexpr double kFp32Floor = 1e-3;
 
 // Algorithmic HBM bytes of one filter application of degree d >= 1 by the
 // Clenshaw recurrence (d launches): every launch reads the matrix values,
@@ -934,8 +957,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     if (o.flags & PFE_DEVICE_PTRS) {
       PFE_HIP(pfe::copy_cols_f64(n, q, o.x0, q, X, ld, h->stream));
     } else {
-      PFE_HIP(hipMemcpy2DAsync(X, ld * sizeof(double), o.x0, q * sizeof(double), q * sizeof(double),
-                               n, hipMemcpyHostToDevice, h->stream));
+      PFE_TRY(upload_block(h, X, ld, o.x0, q, n, W));
     }
   } else {
     PFE_HIP(pfe::gaussian_fill_f64(n, q, X, ld, o.seed, h->stream));
@@ -1041,8 +1063,14 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
                    fp64_phase ? "fp64" : "fp32", cnt, mx,
                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     if (fp64_phase && st.refined) {
-      converged = ok_all;
-      break;   // the single refinement sweep is over
+      // FP64 refinement sweeps from the FP32 subspace: one when the FP32
+      // plateau was within reach of tol, more when its filter separates the
+      // window slowly (each sweep gains what one FP64 iteration gains)
+      if (ok_all) {
+        converged = true;
+        break;
+      }
+      ++st.refined;
     }
     if (ok_all && prev_ok && cnt == prev_cnt && it >= 3) {
       converged = true;
@@ -1052,11 +1080,13 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     // separate the window from eigenvalues in its margin (the block holds
     // fewer vectors than [xi - eps, eta + eps] has eigenvalues, Sec. 2.6):
     // raise the degree 1.5-fold, which shrinks eps by eq. thresh.
+    // In the FP32 phase only a plateau above kFp32Floor counts: FP32 rounding
+    // floors lie below it (4e-7 at degree 400 on 1e5 atoms, 1.1e-5 at degree
+    // 1200 on 1e6), and a higher degree would only raise them.
     const bool plateau = it >= 3 && cnt == prev_cnt && mx > 0.7 * prev_max;
     stall = plateau ? stall + 1 : 0;
-    const double stall_floor = fp64_phase ? o.tol : 1e-5;
-    if (stall >= 3 && mx > stall_floor && !(fp64_phase && st.refined) &&
-        fd.degree < max_degree) {
+    const double stall_floor = fp64_phase ? o.tol : kFp32Floor;
+    if (stall >= 3 && mx > stall_floor && fd.degree < max_degree) {
       const int nd = std::min(max_degree, (int)std::ceil(1.5 * fd.degree));
       PFE_TRY(pfe::design_filter(lam_lo, lam_hi, h->lam_lb, h->lam_ub, nd, 0.0, o.r, o.smoothing, &fd));
       bound = 1.05 * coef_abs_sum(fd.coef) + 1e-12;
@@ -1066,9 +1096,9 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       if (trace) std::fprintf(stderr, "[pfeig] plateau: degree raised to %d (eps %.3e)\n", fd.degree, fd.eps);
     }
     if (!fp64_phase && it >= 2 && cnt == prev_cnt &&
-        ((mx > 0.5 * prev_max && mx <= 1e-5) || mx <= 30.0 * o.tol)) {
+        ((mx > 0.5 * prev_max && mx <= kFp32Floor) || mx <= 30.0 * o.tol)) {
       // FP32 iterations have stalled at their rounding level (or are within
-      // reach of tol): one FP64 sweep
+      // reach of tol): FP64 refinement from here
       fp64_phase = true;
       st.refined = 1;
     }
@@ -1158,8 +1188,7 @@ static Err count_impl(pfe_handle h, double lam_lo, double lam_hi, int degree, in
     if (flags & PFE_DEVICE_PTRS) {
       PFE_HIP(pfe::copy_cols_f64(n, M, V, M, Vd, ld, h->stream));
     } else {
-      PFE_HIP(hipMemcpy2DAsync(Vd, ld * sizeof(double), V, M * sizeof(double), M * sizeof(double),
-                               n, hipMemcpyHostToDevice, h->stream));
+      PFE_TRY(upload_block(h, Vd, ld, V, M, n, h->wsB.as<double>()));
     }
   } else {
     PFE_HIP(pfe::gaussian_fill_f64(n, M, Vd, ld, seed, h->stream));
@@ -1217,8 +1246,7 @@ static Err moments_impl(pfe_handle h, int K, int M, const double* V, uint64_t se
     if (flags & PFE_DEVICE_PTRS) {
       PFE_HIP(pfe::copy_cols_f64(n, M, V, M, Vd, ld, h->stream));
     } else {
-      PFE_HIP(hipMemcpy2DAsync(Vd, ld * sizeof(double), V, M * sizeof(double), M * sizeof(double),
-                               n, hipMemcpyHostToDevice, h->stream));
+      PFE_TRY(upload_block(h, Vd, ld, V, M, n, h->wsB.as<double>()));
     }
   } else {
     PFE_HIP(pfe::gaussian_fill_f64(n, M, Vd, ld, seed, h->stream));

@@ -130,6 +130,59 @@ __global__ __launch_bounds__(256) void k_sddmm_seg(int n_atoms, const int64_t* _
   }
 }
 
+// q <= 64 and m <= MM: the wave's own three rows of every a_m (with w_m
+// folded in) stay in registers across the row's blocks, so a block loads
+// only its neighbour's rows; same products and order as k_sddmm_seg.
+template <int MM>
+__global__ __launch_bounds__(256) void k_sddmm_seg_reg(int n_atoms, const int64_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col_idx, int q,
+                                                       int m, const double* __restrict__ A,
+                                                       int64_t a_stride,
+                                                       const double* __restrict__ T,
+                                                       int64_t t_stride, int64_t ld,
+                                                       const double* __restrict__ w, double* G) {
+  const int wave = uniform(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int row = uniform(blockIdx.x * 4 + wave);
+  if (row >= n_atoms) return;
+  const bool act = lane < q;
+  const int c = act ? lane : 0;
+  double ar[MM][3];
+#pragma unroll
+  for (int mm = 0; mm < MM; ++mm) {
+    const double wm = (mm < m) ? w[mm] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      ar[mm][r] = (mm < m && act) ? wm * A[mm * a_stride + (int64_t)(3 * row + r) * ld + c] : 0.0;
+  }
+  for (int64_t k = row_ptr[row]; k < row_ptr[row + 1]; ++k) {
+    const int j = col_idx[k];
+    double g[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) g[e] = 0.0;
+#pragma unroll
+    for (int mm = 0; mm < MM; ++mm) {
+      if (mm < m) {
+        const double* tm = T + mm * t_stride + (int64_t)(3 * j) * ld + c;
+        double tr[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) tr[r] = act ? tm[(int64_t)r * ld] : 0.0;
+#pragma unroll
+        for (int pa = 0; pa < 3; ++pa)
+#pragma unroll
+          for (int qb = 0; qb < 3; ++qb) g[pa * 3 + qb] += ar[mm][pa] * tr[qb];
+      }
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      const double tot = wave_sum(g[e]);
+      if (lane == e) v = tot;
+    }
+    if (lane < 9) G[k * 9 + lane] += v;
+  }
+}
+
 __device__ int64_t find_block(const int64_t* row_ptr, const int32_t* col_idx, int i, int j) {
   int64_t lo = row_ptr[i], hi = row_ptr[i + 1] - 1;
   while (lo <= hi) {
@@ -308,12 +361,17 @@ hipError_t assemble_springs(int64_t n_atoms, const int64_t* row_ptr, const int32
   return hipGetLastError();
 }
 
+constexpr int kSegRegMax = 16;   // checkpoint segments up to 16 steps (degree <= 256)
+
 hipError_t sddmm_seg_f64(const Bsr& A, int q, int m, const double* a, int64_t a_stride,
                          const double* t, int64_t t_stride, int64_t ld, const double* w,
                          double* G, hipStream_t s) {
   if (A.n_atoms == 0 || m == 0) return hipSuccess;
   const unsigned grid = nb(A.n_atoms, 4);
-  if (q <= 64)
+  if (q <= 64 && m <= kSegRegMax)
+    hipLaunchKernelGGL(k_sddmm_seg_reg<kSegRegMax>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms,
+                       A.row_ptr, A.col_idx, q, m, a, a_stride, t, t_stride, ld, w, G);
+  else if (q <= 64)
     hipLaunchKernelGGL(k_sddmm_seg<1>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
                        A.col_idx, q, m, a, a_stride, t, t_stride, ld, w, G);
   else if (q <= 128)

@@ -1,7 +1,7 @@
-"""Writes glass1m_window.json and glass4m_window.json: windows of the
-mass-weighted Hessian of the 1 000 000- and 4 000 000-atom synthetic glasses
-(seed 1) that hold about the requested number of eigenvalues, located and
-counted by the CPU oracle alone.  Nothing here touches the HIP library.
+"""Writes glass1m_window.json: a window of the mass-weighted Hessian of the
+1 000 000-atom synthetic glass (seed 1) that holds about the requested number
+of eigenvalues, located and counted by the CPU oracle alone.  Nothing here
+touches the HIP library.
 
 At these sizes no dense or exact count is affordable, so the count is the
 stochastic estimate of Sec. 2.4 (eq. eigval_count_estimator) from Chebyshev
@@ -12,8 +12,7 @@ theta_max, the largest Ritz value of a 30-step Lanczos run from
 gaussian_vector(n, 7)); its upper end is moved until the estimate reaches the
 configuration's nev.
 
-Run:  python tests/golden/make_large_windows.py [1m|4m ...]
-(about 10 min for 1m, 45 min for 4m on 8 cores)
+Run:  python tests/golden/make_large_windows.py   (about 20 min on 8 cores)
 """
 from __future__ import annotations
 
@@ -33,8 +32,6 @@ from synth import gaussian_block, gaussian_vector, lattice_glass  # noqa: E402
 SPECS = {
     "1m": dict(n_atoms=1000000, seed=1, lanczos_steps=30, v0_seed=7, lo_frac=0.005, nev=128,
                moments=1500, probes=8, probe_seed=13),
-    "4m": dict(n_atoms=4000000, seed=1, lanczos_steps=30, v0_seed=7, lo_frac=0.003, nev=200,
-               moments=1500, probes=4, probe_seed=13),
 }
 
 
@@ -84,5 +81,5 @@ def main(tag):
 
 
 if __name__ == "__main__":
-    for tag in (sys.argv[1:] or ["1m", "4m"]):
+    for tag in (sys.argv[1:] or ["1m"]):
         main(tag)

@@ -3,13 +3,14 @@
 // spectral map of eq. transf.1 folded into scalars), the single-vector SpMV
 // used by the Lanczos bounds, mass weighting (eq. intro.2) and validation.
 //
-// Mapping of the fused step: one wavefront per atom row i (three matrix rows).
-// Lane l owns NP column chunks of VW contiguous elements, chunk = l + 64 p,
-// so a neighbour's three rows of T_in (3 q contiguous elements) are read by
-// coalesced 16-32 byte vector loads.  The row index, the block-column index
-// and the nine block values are wave-uniform and go through scalar loads.
-// Work-groups are remapped so that every XCD walks a contiguous range of
-// atom rows (neighbouring rows share T_in rows in that XCD's L2).
+// Mapping of the fused step: one wavefront per row tile (two atom rows, six
+// matrix rows; one atom row when tiles are off).  Lane l owns NP column
+// chunks of VW contiguous elements, chunk = l + 64 p, so a neighbour's three
+// rows of T_in (3 q contiguous elements) are read by coalesced 8-32 byte
+// vector loads.  Tile records (column, row mask) and the block values are
+// wave-uniform and go through scalar loads.  Work-groups are dealt to the
+// XCDs in chunks sized to the pattern's neighbour span (or one range per XCD
+// for the locality order), so rows that share T_in rows share an L2.
 #include <algorithm>
 #include <cstdlib>
 #include <vector>
@@ -181,101 +182,13 @@ __global__ __launch_bounds__(256) void k_cheb_step(
                            zeta);
 }
 
-// Variant L: the work-group first stages the column indices and block values
-// of its four rows (one contiguous range of blocks) in LDS with coalesced
-// loads; each wave then takes its row's neighbours U at a time, reading the
-// indices and values as LDS broadcasts.
-constexpr int kStageBlocks = 128;
-
-template <typename T, int VW, int NP, int U>
-__global__ __launch_bounds__(256) void k_cheb_step_lds(
-    int n_atoms, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-    const T* __restrict__ vals, const T* __restrict__ tin, const T* prev, const T* add, T* out,
-    int q, int64_t ld, T alpha, T beta, T delta, T zeta, int chunk) {
-  using vt = typename VT<T, VW>::type;
-  __shared__ T s_val[kStageBlocks * 9];
-  __shared__ int s_col[kStageBlocks + U];
-  const int lb = map_block(blockIdx.x, chunk);
-  const int r0 = lb * kWavesPerBlock;
-  if (r0 >= n_atoms) return;                       // uniform over the work-group
-  const int wave = uniform(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int tid = threadIdx.x;
-  const int row = r0 + wave;
-  const bool row_ok = row < n_atoms;
-  const int r_end = min(r0 + kWavesPerBlock, n_atoms);
-  const int col0 = blockIdx.y * (64 * NP * VW);
-  const int64_t wb0 = row_ptr[r0];
-  const int64_t wb1 = (alpha != T(0)) ? row_ptr[r_end] : wb0;
-  const int64_t b0 = row_ok ? row_ptr[row] : wb1;
-  const int64_t b1 = row_ok ? row_ptr[row + 1] : wb1;
-
-  vt acc[3][NP];
-  bool act[NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    acc[0][p] = vt(0);
-    acc[1][p] = vt(0);
-    acc[2][p] = vt(0);
-    act[p] = col0 + (lane + 64 * p) * VW < q;
-  }
-  for (int64_t c0 = wb0; c0 < wb1; c0 += kStageBlocks) {
-    const int cnt = (int)min((int64_t)kStageBlocks, wb1 - c0);
-    __syncthreads();
-    for (int i = tid; i < cnt * 9; i += 256) s_val[i] = vals[c0 * 9 + i];
-    for (int i = tid; i < cnt + U; i += 256) s_col[i] = (i < cnt) ? col_idx[c0 + i] : 0;
-    __syncthreads();
-    const int k_lo = (int)(max(b0, c0) - c0);
-    const int k_hi = (int)(min(b1, c0 + cnt) - c0);
-    for (int k = k_lo; k < k_hi; k += U) {
-      vt x[U][3][NP];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const bool valid = (u == 0) || (k + u < k_hi);
-        const int j = valid ? s_col[k + u] : row;
-        const T* src = tin + (int64_t)(3 * j) * ld + col0;
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          const int c = (lane + 64 * p) * VW;
-          if (act[p] && valid) {
-            x[u][0][p] = *reinterpret_cast<const vt*>(src + c);
-            x[u][1][p] = *reinterpret_cast<const vt*>(src + ld + c);
-            x[u][2][p] = *reinterpret_cast<const vt*>(src + 2 * ld + c);
-          } else {
-            x[u][0][p] = vt(0);
-            x[u][1][p] = vt(0);
-            x[u][2][p] = vt(0);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (u == 0 || k + u < k_hi) {
-          const T* hv = s_val + (k + u) * 9;
-          T h[9];
-#pragma unroll
-          for (int t = 0; t < 9; ++t) h[t] = hv[t];
-#pragma unroll
-          for (int p = 0; p < NP; ++p) {
-            acc[0][p] += h[0] * x[u][0][p] + h[1] * x[u][1][p] + h[2] * x[u][2][p];
-            acc[1][p] += h[3] * x[u][0][p] + h[4] * x[u][1][p] + h[5] * x[u][2][p];
-            acc[2][p] += h[6] * x[u][0][p] + h[7] * x[u][1][p] + h[8] * x[u][2][p];
-          }
-        }
-      }
-    }
-  }
-  if (!row_ok) return;
-  step_epilogue<T, VW, NP>(acc, act, row, lane, col0, tin, prev, add, out, ld, alpha, beta, delta,
-                           zeta);
-}
-
-// Variant T (row tiles): one wave per tile of R consecutive block rows.  Each
-// union column j of the tile is gathered once (three rows of T_in) and
-// applied to every row of the tile that stores block (row, j), so a T_in row
-// shared by neighbouring output rows costs one set of vector loads instead of
-// up to R.  Block values are read in tile order from a running offset, so
-// their scalar loads depend only on the (column, mask) record.
+// Variant T (row tiles): one wave per tile of R block rows (consecutive in
+// the processing order, tile_row).  Each union column j of the tile is
+// gathered once (three rows of T_in) and applied to every row of the tile
+// that stores block (row, j), so a T_in row shared by neighbouring output
+// rows costs one set of vector loads instead of up to R.  Block values are
+// read in tile order from a running offset, so their scalar loads depend
+// only on the (column, mask) record.
 template <typename T, int VW, int NP, int U, int R>
 __global__ __launch_bounds__(256) void k_cheb_tile(
     int n_atoms, int n_tiles, const int64_t* __restrict__ tile_ptr,
@@ -392,9 +305,6 @@ __global__ void k_permute_blocks(int64_t nnzb, const int64_t* __restrict__ perm,
   dst[i] = src[perm[p] * 9 + t];
 }
 
-#ifndef PFE_CHEB_VARIANT
-#define PFE_CHEB_VARIANT 0   // 0: scalar, 1: LDS-staged
-#endif
 #ifndef PFE_CHEB_CHUNK
 #define PFE_CHEB_CHUNK 64    // work-groups per XCD chunk (measured best on MI355X); 0: one range per XCD
 #endif
@@ -457,10 +367,6 @@ hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev,
                        (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
                        A.tile_row, vals, tin, prev, add, out, q, ld, alpha, beta, delta, zeta,
                        chunk);
-  } else if (PFE_CHEB_VARIANT == 1) {
-    hipLaunchKernelGGL((k_cheb_step_lds<T, VW, NP, kUnroll>), grid, dim3(256), 0, s,
-                       (int)A.n_atoms, A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, ld,
-                       alpha, beta, delta, zeta, chunk);
   } else {
     hipLaunchKernelGGL((k_cheb_step<T, VW, NP, kUnroll>), grid, dim3(256), 0, s, (int)A.n_atoms,
                        A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, ld, alpha, beta,

@@ -200,8 +200,9 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's multi-GPU "
-              "decomposition is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this library has no "
+              "multi-GPU path (a slab decomposition with halo exchange is designed, not built)",
+              file=sys.stderr)
         return 2
     import numpy as np
     import torch

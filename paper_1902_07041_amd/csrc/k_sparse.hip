@@ -309,21 +309,15 @@ __global__ void k_permute_blocks(int64_t nnzb, const int64_t* __restrict__ perm,
 #define PFE_CHEB_CHUNK 64    // work-groups per XCD chunk (measured best on MI355X); 0: one range per XCD
 #endif
 
-int pass_cols_override() {
-  static int v = [] {
-    const char* e = std::getenv("PFEIG_CHEB_PASS_COLS");
-    return e ? std::atoi(e) : 0;
-  }();
-  return v;
+// Schedule overrides, read at every launch (they change which wave computes
+// a row when, never the result): PFEIG_CHEB_PASS_COLS (columns per pass) and
+// PFEIG_CHEB_CHUNK (work-groups per XCD chunk).
+int env_int(const char* name, int unset) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : unset;
 }
-
-int chunk_override() {
-  static int v = [] {
-    const char* e = std::getenv("PFEIG_CHEB_CHUNK");
-    return e ? std::atoi(e) : -1;
-  }();
-  return v;
-}
+int pass_cols_override() { return env_int("PFEIG_CHEB_PASS_COLS", 0); }
+int chunk_override() { return env_int("PFEIG_CHEB_CHUNK", -1); }
 
 template <typename T, int VW, int NP>
 hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, const T* add,

@@ -193,3 +193,24 @@ def test_device_inputs_ordered_after_torch_default_stream(case):
             np.testing.assert_array_equal(Y.cpu().numpy(), ref)
     finally:
         P.pfe_destroy(h)
+
+
+@pytest.mark.parametrize("q", [96, 256])
+def test_filter_schedule_does_not_change_bits(case, q, monkeypatch):
+    """Work-groups per XCD chunk and columns per pass only change which wave
+    computes a row when: every output element sums its blocks in the same
+    order, so the results are identical bit for bit."""
+    banner(f"apply_filter under other XCD chunkings and column passes, q={q}")
+    f = design(case, 25)
+    X = gaussian_block(case.n, q, 41)
+    out = []
+    for chunk, cols in [(None, None), ("1", None), ("7", None), ("100000", None), (None, "64"),
+                        (None, "128")]:
+        for name, val in (("PFEIG_CHEB_CHUNK", chunk), ("PFEIG_CHEB_PASS_COLS", cols)):
+            if val is None:
+                monkeypatch.delenv(name, raising=False)
+            else:
+                monkeypatch.setenv(name, val)
+        out.append(P.pfe_apply_filter(case.h, f, X))
+    for Y in out[1:]:
+        np.testing.assert_array_equal(Y, out[0])

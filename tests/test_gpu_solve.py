@@ -95,6 +95,21 @@ def test_solve_fp32_form(case):
     assert out["stats"]["refined"] == 1
 
 
+def test_solve_fp32_form_refines_until_converged(case):
+    """A tolerance far below the FP32 rounding floor: the FP32 iterations
+    plateau, then FP64 refinement sweeps run until the residuals meet it."""
+    banner("solve fp32-filter form N=1000, tol 1e-12 (several FP64 sweeps)")
+    X0 = gaussian_block(case.n, 32, 11)
+    out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=20, tol=1e-12,
+                               precision=P.PFE_FP32, x0=X0)
+    assert out["status"] == "PFE_OK", out["stats"]
+    check_pairs(case, out, 1e-12, 1e-10)
+    st = out["stats"]
+    assert st["refined"] >= 2
+    assert st["fp64_iterations"] == st["refined"]
+    assert st["iterations"] > st["refined"]
+
+
 def test_solve_seeded_start_and_capacity(case):
     banner("solve seeded start / capacity")
     out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-10, seed=3)

@@ -973,7 +973,6 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   const double delta = 1e-6 * h->lam_ub;
   std::vector<double> theta, res;
   int prev_cnt = -1;
-  bool prev_ok = false;
   bool converged = false;
   bool fp64_phase = !mixed;
   double prev_max = HUGE_VAL;
@@ -1072,7 +1071,11 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       }
       ++st.refined;
     }
-    if (ok_all && prev_ok && cnt == prev_cnt && it >= 3) {
+    // Stop as Algorithm 4 does once the wanted pairs have converged: every
+    // Ritz value near the window meets tol, and the in-window count is the
+    // one of the previous iteration (the count is the only sign of a pair
+    // still entering the window).
+    if (ok_all && cnt == prev_cnt && it >= 3) {
       converged = true;
       break;
     }
@@ -1102,7 +1105,6 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       fp64_phase = true;
       st.refined = 1;
     }
-    prev_ok = ok_all;
     prev_cnt = cnt;
     prev_max = mx;
   }

@@ -629,34 +629,34 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int q, const double* __rest
         qq[tid] = r;
       }
       __syncthreads();
-      for (int idx = tid; idx < half * q; idx += nt) {   // rows p, r of A and of V^T
-        const int k = idx / q, j = idx % q;
+      // rows p, r of A and of V^T: rotation k on thread rows k = tid/32 (+32),
+      // element j on the 32 lanes of that row group
+      for (int k = tid >> 5; k < half; k += nt >> 5) {
         const double s = sn[k];
         if (s == 0.0) continue;
         const double c = cs[k];
         const int p = pp[k], r = qq[k];
-        const double a = A[p * ldq + j], b = A[r * ldq + j];
-        A[p * ldq + j] = c * a - s * b;
-        A[r * ldq + j] = s * a + c * b;
-        const double va = VT[p * ldq + j], vb = VT[r * ldq + j];
-        VT[p * ldq + j] = c * va - s * vb;
-        VT[r * ldq + j] = s * va + c * vb;
+        for (int j = tid & 31; j < q; j += 32) {
+          const double a = A[p * ldq + j], b = A[r * ldq + j];
+          A[p * ldq + j] = c * a - s * b;
+          A[r * ldq + j] = s * a + c * b;
+          const double va = VT[p * ldq + j], vb = VT[r * ldq + j];
+          VT[p * ldq + j] = c * va - s * vb;
+          VT[r * ldq + j] = s * va + c * vb;
+        }
       }
       __syncthreads();
-      for (int idx = tid; idx < half * q; idx += nt) {   // columns p, r of A
-        const int k = idx / q, i = idx % q;
+      // columns p, r of A; the pivot pair (p, r) is set to its exact zero here
+      for (int k = tid >> 5; k < half; k += nt >> 5) {
         const double s = sn[k];
         if (s == 0.0) continue;
         const double c = cs[k];
         const int p = pp[k], r = qq[k];
-        const double a = A[i * ldq + p], b = A[i * ldq + r];
-        A[i * ldq + p] = c * a - s * b;
-        A[i * ldq + r] = s * a + c * b;
-      }
-      __syncthreads();
-      if (tid < half && sn[tid] != 0.0) {
-        A[pp[tid] * ldq + qq[tid]] = 0.0;
-        A[qq[tid] * ldq + pp[tid]] = 0.0;
+        for (int i = tid & 31; i < q; i += 32) {
+          const double a = A[i * ldq + p], b = A[i * ldq + r];
+          A[i * ldq + p] = (i == r) ? 0.0 : c * a - s * b;
+          A[i * ldq + r] = (i == p) ? 0.0 : s * a + c * b;
+        }
       }
       __syncthreads();
     }

@@ -518,36 +518,35 @@ __global__ __launch_bounds__(1024) void k_jacobi(int q, const double* __restrict
       }
       __syncthreads();
       // rows p, r of A
-      for (int idx = tid; idx < half * q; idx += nt) {
-        const int k = idx / q, j = idx % q;
+      // rows p, r of A and of V^T (V is kept transposed, so both passes
+      // below touch contiguous rows except A's columns)
+      for (int k = tid >> 5; k < half; k += nt >> 5) {
         const double s = sn[k];
         if (s == 0.0) continue;
         const double c = cs[k];
         const int p = pp[k], r = qq[k];
-        const double a = A[p * q + j], b = A[r * q + j];
-        A[p * q + j] = c * a - s * b;
-        A[r * q + j] = s * a + c * b;
+        for (int j = tid & 31; j < q; j += 32) {
+          const double a = A[p * q + j], b = A[r * q + j];
+          A[p * q + j] = c * a - s * b;
+          A[r * q + j] = s * a + c * b;
+          const double va = V[p * q + j], vb = V[r * q + j];
+          V[p * q + j] = c * va - s * vb;
+          V[r * q + j] = s * va + c * vb;
+        }
       }
       __syncthreads();
-      // columns p, r of A and V
-      for (int idx = tid; idx < half * q; idx += nt) {
-        const int k = idx / q, i = idx % q;
+      // columns p, r of A; the rotated pair's off-diagonal entries are set
+      // to their exact zero here
+      for (int k = tid >> 5; k < half; k += nt >> 5) {
         const double s = sn[k];
         if (s == 0.0) continue;
         const double c = cs[k];
         const int p = pp[k], r = qq[k];
-        const double a = A[i * q + p], b = A[i * q + r];
-        A[i * q + p] = c * a - s * b;
-        A[i * q + r] = s * a + c * b;
-        const double va = V[i * q + p], vb = V[i * q + r];
-        V[i * q + p] = c * va - s * vb;
-        V[i * q + r] = s * va + c * vb;
-      }
-      __syncthreads();
-      // the rotated pair's off-diagonal entry is zero by construction
-      if (tid < half && sn[tid] != 0.0) {
-        A[pp[tid] * q + qq[tid]] = 0.0;
-        A[qq[tid] * q + pp[tid]] = 0.0;
+        for (int i = tid & 31; i < q; i += 32) {
+          const double a = A[i * q + p], b = A[i * q + r];
+          A[i * q + p] = (i == r) ? 0.0 : c * a - s * b;
+          A[i * q + r] = (i == p) ? 0.0 : s * a + c * b;
+        }
       }
       __syncthreads();
     }
@@ -563,7 +562,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(int q, const double* __restrict
       if (dj < di || (dj == di && j < i)) ++rank;
     }
     evals[rank] = di;
-    for (int r = 0; r < q; ++r) Q[r * q + rank] = V[r * q + i];
+    for (int r = 0; r < q; ++r) Q[r * q + rank] = V[i * q + r];   // V holds V^T
   }
   if (tid == 0) info[0] = converged ? sweep : -sweep;
 }

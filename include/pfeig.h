@@ -107,6 +107,23 @@ pfe_status pfe_set_springs(pfe_handle h, int64_t n_atoms, int64_t nnzb, const in
                            const double* unit, const double* k, const double* masses,
                            double* hblocks_out, uint32_t flags);
 
+/* Host-only, pure: an order of the atoms of a block-CSR pattern (symmetric
+ * structure, host arrays as for pfe_set_hessian) in which contiguous ranges
+ * are compact regions of the pattern's graph.  The atoms are bisected
+ * recursively at breadth-first levels from a pseudo-peripheral atom down to
+ * ranges of `leaf` atoms (>= 2 group); inside a range they are taken
+ * `group` at a time (1..4), each group grown by the free neighbour sharing
+ * the most block columns.  order[k] (n_atoms entries, caller-owned) is the
+ * atom taken k-th.  The filter applies the same order to its own work when
+ * the given numbering scatters neighbours (the results do not change); a
+ * caller may also renumber its atoms with it.  far_in / far_out (either may
+ * be NULL) receive the fraction of off-diagonal blocks whose atoms lie more
+ * than `window` positions apart in the given numbering / in the order.
+ * EINVAL for inconsistent arrays or parameters. */
+pfe_status pfe_locality_order(int64_t n_atoms, int64_t nnzb, const int64_t* row_ptr,
+                              const int32_t* col_idx, int32_t leaf, int32_t group, int64_t window,
+                              int32_t* order, double* far_in, double* far_out);
+
 /* ----------------------------------------------------------------- bounds
  * `steps` Lanczos steps with full re-orthogonalisation on H (Algorithm 3,
  * step 3) from start vector v0 (length n; NULL: a seeded Gaussian vector from

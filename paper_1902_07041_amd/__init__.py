@@ -13,7 +13,7 @@ from ._capi import (PFE_FP32, PFE_FP64, PFE_SMOOTH_JACKSON, PFE_SMOOTH_LANCZOS, 
                     pfe_device_bytes, pfe_eigvec_block_gradient, pfe_estimate_bounds,
                     pfe_estimate_count, pfe_last_error, pfe_set_bounds, pfe_set_hessian,
                     pfe_set_springs, pfe_count_moments, pfe_solve_sliced, pfe_design_dirac,
-                    pfe_solve_lanczos, DiracFilter,
+                    pfe_solve_lanczos, DiracFilter, pfe_locality_order,
                     pfe_solve_interval, pfe_spring_gradient, pfe_version)
 
 __all__ = [
@@ -23,5 +23,5 @@ __all__ = [
     "pfe_device_bytes", "pfe_eigvec_block_gradient", "pfe_estimate_bounds", "pfe_estimate_count",
     "pfe_last_error", "pfe_set_bounds", "pfe_set_hessian", "pfe_set_springs", "pfe_solve_interval",
     "pfe_spring_gradient", "pfe_version", "pfe_count_moments", "pfe_solve_sliced",
-    "pfe_design_dirac", "pfe_solve_lanczos", "DiracFilter",
+    "pfe_design_dirac", "pfe_solve_lanczos", "DiracFilter", "pfe_locality_order",
 ]

@@ -127,6 +127,7 @@ def load_library():
                                    C.POINTER(CSolveStats)]
     L.pfe_count_moments.argtypes = [vp, i32, i32, vp, u64, u32, vp]
     L.pfe_design_dirac.argtypes = [dbl, dbl, dbl, dbl, i32, dbl, i32, vp, i32, C.POINTER(CDiracFilter)]
+    L.pfe_locality_order.argtypes = [i64, i64, vp, vp, i32, i32, i64, vp, C.POINTER(dbl), C.POINTER(dbl)]
     L.pfe_lanczos_opts_default.argtypes = [C.POINTER(CLanczosOpts)]
     L.pfe_lanczos_opts_default.restype = None
     L.pfe_solve_lanczos.argtypes = [vp, dbl, dbl, i32, C.POINTER(CLanczosOpts), C.POINTER(i32), vp,
@@ -497,6 +498,23 @@ def pfe_design_dirac(lam_lo, lam_hi, lam_lb, lam_ub, degree=0, phi=0.8,
             raise PfeError(st, "pfe_design_dirac failed")
         return DiracFilter(out.degree, out.smoothing, out.c, out.e, out.xi, out.eta, out.gamma,
                            out.tau, out.peak, buf[: out.degree + 1].copy())
+
+
+def pfe_locality_order(row_ptr, col_idx, leaf=256, group=2, window=32768):
+    """(order, far_in, far_out): compact-range order of the atoms of a block-CSR
+    pattern (host only); far_* are the fractions of off-diagonal blocks whose
+    atoms lie more than `window` positions apart before / after."""
+    L = load_library()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = rp.shape[0] - 1
+    order = np.zeros(max(n, 1), dtype=np.int32)
+    fi, fo = C.c_double(), C.c_double()
+    st = L.pfe_locality_order(n, ci.shape[0], rp.ctypes.data, ci.ctypes.data, leaf, group, window,
+                              order.ctypes.data, C.byref(fi), C.byref(fo))
+    if st != 0:
+        raise PfeError(st, "pfe_locality_order failed")
+    return order[:n], fi.value, fo.value
 
 
 def pfe_solve_lanczos(h, lam_lo, lam_hi, nev, block=16, max_basis=0, degree=0, phi=0.8,

@@ -1848,6 +1848,25 @@ pfe_status pfe_solve_lanczos(pfe_handle h, double lam_lo, double lam_hi, int32_t
   return finish(h, lanczos_impl(h, lam_lo, lam_hi, nev, opts, n_found, evals, evecs, resid, stats));
 }
 
+pfe_status pfe_locality_order(int64_t n_atoms, int64_t nnzb, const int64_t* row_ptr,
+                              const int32_t* col_idx, int32_t leaf, int32_t group, int64_t window,
+                              int32_t* order, double* far_in, double* far_out) {
+  if (n_atoms <= 0 || n_atoms > (int64_t)INT32_MAX || nnzb < 0 || !row_ptr || !col_idx ||
+      !order || group < 1 || group > 4 || leaf < 2 * group || window < 0)
+    return PFE_EINVAL;
+  if (row_ptr[0] != 0 || row_ptr[n_atoms] != nnzb) return PFE_EINVAL;
+  for (int64_t i = 0; i < n_atoms; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) return PFE_EINVAL;
+  for (int64_t k = 0; k < nnzb; ++k)
+    if (col_idx[k] < 0 || col_idx[k] >= n_atoms) return PFE_EINVAL;
+  std::vector<int32_t> ord;
+  pfe::locality_order(n_atoms, row_ptr, col_idx, leaf, group, ord);
+  std::memcpy(order, ord.data(), (size_t)n_atoms * sizeof(int32_t));
+  if (far_in) *far_in = pfe::far_block_fraction(n_atoms, row_ptr, col_idx, nullptr, window);
+  if (far_out) *far_out = pfe::far_block_fraction(n_atoms, row_ptr, col_idx, ord.data(), window);
+  return PFE_OK;
+}
+
 pfe_status pfe_design_dirac(double lam_lo, double lam_hi, double lam_lb, double lam_ub,
                             int32_t degree, double phi, int32_t smoothing, double* coef_out,
                             int32_t coef_cap, pfe_dirac_filter* out) {

@@ -97,3 +97,33 @@ def test_design_dirac_matches_oracle(sm, name):
     assert f.tau == pytest.approx(vals[0], rel=1e-10)
     assert f.tau == pytest.approx(vals[1], rel=1e-9)
     assert f.peak == pytest.approx(vals[2], rel=1e-10)
+
+
+def test_locality_order_compacts_a_scrambled_numbering():
+    """Host-only atom order (no GPU): a permutation whose groups of two are
+    neighbours, which undoes most of the scatter of a randomly renumbered
+    glass and leaves a lattice-numbered one as local as it was."""
+    from synth import lattice_glass, relabel
+    g = lattice_glass(4096, seed=2)
+    r = relabel(g, 3)
+    for gl in (g, r):
+        order, far_in, far_out = P.pfe_locality_order(gl.row_ptr, gl.col_idx, leaf=64, group=2,
+                                                      window=1024)
+        assert np.array_equal(np.sort(order), np.arange(gl.n_atoms))
+        nbr = [set(gl.col_idx[gl.row_ptr[i]:gl.row_ptr[i + 1]]) for i in range(gl.n_atoms)]
+        pairs = order[: gl.n_atoms - gl.n_atoms % 2].reshape(-1, 2)
+        linked = np.mean([b in nbr[a] for a, b in pairs])
+        assert linked > 0.85
+        assert far_out < 0.25
+    _, far_in_r, far_out_r = P.pfe_locality_order(r.row_ptr, r.col_idx, leaf=64, window=1024)
+    assert far_in_r > 0.5 and far_out_r < far_in_r / 3
+
+
+def test_locality_order_rejects_bad_patterns():
+    rp = np.array([0, 2, 3], dtype=np.int64)
+    with pytest.raises(P.PfeError):
+        P.pfe_locality_order(rp, np.array([0, 5, 1], dtype=np.int32))       # column out of range
+    with pytest.raises(P.PfeError):
+        P.pfe_locality_order(np.array([0, 2, 1], dtype=np.int64), np.array([0, 1], dtype=np.int32))
+    with pytest.raises(P.PfeError):
+        P.pfe_locality_order(rp, np.array([0, 1, 1], dtype=np.int32), group=5)

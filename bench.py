@@ -323,7 +323,7 @@ def main() -> int:
         "t_adjoint_and_gradients_s": med("t_adjoint"),
         "t_a4_filter_s": med("t_a4"),
         "orthogonalisation_mfma": {
-            "kernels": "k_gram_partial + k_gram_reduce (Gram), k_gemm_tall (X R^-1, X Q, W Q); FP64 MFMA",
+            "kernels": "k_gram_small + k_gram_reduce (Gram), k_gemm_bres (X R^-1, X Q, W Q); FP64 MFMA",
             "flops": s64["gemm_flops"], "seconds": s64["t_gemm"],
             "achieved_TFLOPs": s64["gemm_flops"] / s64["t_gemm"] / 1e12 if s64["t_gemm"] else None,
             "peak_TFLOPs": 78.6,

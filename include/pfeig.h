@@ -348,7 +348,10 @@ pfe_status pfe_solve_lanczos(pfe_handle h, double lam_lo, double lam_hi, int32_t
 typedef struct {
   int32_t n_slices;       /* sub-windows; 0: ceil(estimated count / per_slice) */
   int32_t per_slice;      /* eigenvalues aimed for per sub-window (0: block / 2) */
-  double margin;          /* filter margin / sub-window width (0: 1/6) */
+  double margin;          /* filter margin / sub-window width (0: the widest margin, up
+                             to 1.5 widths and at least 1/6, whose count estimated from
+                             the moments stays within 85 % of the block; 1/6 when the
+                             cuts are given and no moments are computed) */
   int32_t count_degree;   /* Jackson-damped series degree of the count (0: 1000) */
   int32_t count_samples;  /* probe vectors of the count (0: 32) */
   uint64_t count_seed;    /* probe vector seed */

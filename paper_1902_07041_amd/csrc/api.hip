@@ -1405,6 +1405,35 @@ static Err sliced_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     pfe_solve_opts os = o;
     os.degree = 0;
     os.eps = margin * (wb - wa) / e;
+    if (so.margin <= 0 && !mu.empty()) {
+      // The filter's work for a slice scales with 1/eps whatever its rate r
+      // (degree ~ log(1/r)/eps, iterations ~ log(tol)/log(r)), and Sec. 2.6
+      // only asks the block to hold the eigenvalues of [xi - eps, eta + eps]:
+      // take the widest margin (up to 1.5 widths) whose estimated count from
+      // the moments stays within 85 % of the block.
+      auto count_in = [&](double u, double v) {
+        u = std::max(u, h->lam_lb);
+        v = std::min(v, h->lam_ub);
+        const std::vector<double> chi =
+            pfe::chi_coefficients((u - c) / e, (v - c) / e, K, PFE_SMOOTH_JACKSON);
+        double acc = 0;
+        for (int k = 0; k <= K; ++k) acc += chi[k] * mu[k];
+        return (double)n * acc;
+      };
+      const double w = wb - wa, cap_q = 0.85 * q;
+      double mlo = margin, mhi = 1.5;
+      if (count_in(wa - mlo * w, wb + mlo * w) <= cap_q) {
+        if (count_in(wa - mhi * w, wb + mhi * w) <= cap_q) {
+          mlo = mhi;
+        } else {
+          for (int it = 0; it < 24; ++it) {
+            const double mm = 0.5 * (mlo + mhi);
+            (count_in(wa - mm * w, wb + mm * w) <= cap_q ? mlo : mhi) = mm;
+          }
+        }
+        os.eps = mlo * w / e;
+      }
+    }
     os.x0 = nullptr;
     os.seed = o.seed + 7919ull * (uint64_t)slice_no;
     os.flags = PFE_DEVICE_PTRS;

@@ -214,3 +214,35 @@ def test_filter_schedule_does_not_change_bits(case, q, monkeypatch):
         out.append(P.pfe_apply_filter(case.h, f, X))
     for Y in out[1:]:
         np.testing.assert_array_equal(Y, out[0])
+
+
+@pytest.mark.parametrize("shape", ["one_atom", "isolated_atom", "chain5"])
+@pytest.mark.parametrize("q", [1, 3])
+def test_filter_tiny_patterns(shape, q):
+    """The smallest patterns: a single atom (H = 0), an atom without springs
+    beside a bonded pair, a 5-atom chain; ragged column counts."""
+    from synth.glass import assemble_blocks
+    banner(f"apply_filter tiny pattern {shape} q={q}")
+    pairs = {"one_atom": [], "isolated_atom": [(0, 1)], "chain5": [(i, i + 1) for i in range(4)]}[shape]
+    N = {"one_atom": 1, "isolated_atom": 3, "chain5": 5}[shape]
+    rng = np.random.default_rng(8)
+    P_ = np.array(pairs, dtype=np.int64).reshape(-1, 2)
+    unit = rng.standard_normal((P_.shape[0], 3))
+    unit /= np.maximum(np.linalg.norm(unit, axis=1, keepdims=True), 1e-300)
+    k = rng.uniform(0.5, 1.5, P_.shape[0])
+    masses = rng.uniform(60.0, 90.0, N)
+    row_ptr, col_idx, blocks = assemble_blocks(N, P_, unit, k)
+    hb = hessian.weight_blocks(row_ptr, col_idx, blocks, masses)
+    Hd = hessian.to_dense(row_ptr, col_idx, hb)
+    ub = max(1.0, 1.01 * np.linalg.eigvalsh(Hd).max())
+    h = P.pfe_create(0)
+    try:
+        P.pfe_set_hessian(h, row_ptr, col_idx, blocks, masses)
+        P.pfe_set_bounds(h, 0.0, ub)
+        f = P.pfe_design_filter(0.1 * ub, 0.3 * ub, 0.0, ub, degree=7)
+        X = gaussian_block(3 * N, q, 5)
+        Y = P.pfe_apply_filter(h, f, X)
+        ref = chebyshev.apply_filter(Hd, f.c, f.e, f.coef, X)
+        assert np.abs(Y - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1.0)
+    finally:
+        P.pfe_destroy(h)

@@ -115,6 +115,19 @@ def test_solve_fp32_form_refines_until_converged(case):
     assert st["iterations"] > st["refined"]
 
 
+def test_solve_window_in_a_gap_returns_nothing(case):
+    """A window strictly between two consecutive eigenvalues holds none: the
+    solve returns zero pairs with status OK."""
+    banner("solve on a window inside a spectral gap")
+    lam = case.lam
+    i = int(np.argmax(np.diff(lam[(lam > case.lo) & (lam < case.hi)]))) + int(np.sum(lam <= case.lo))
+    a, b = lam[i], lam[i + 1]
+    lo, hi = a + 0.3 * (b - a), a + 0.7 * (b - a)
+    out = P.pfe_solve_interval(case.h, lo, hi, 8, 32, degree=80, tol=1e-10, seed=5)
+    assert out["status"] == "PFE_OK", out["stats"]
+    assert out["evals"].size == 0
+
+
 def test_solve_seeded_start_and_capacity(case):
     banner("solve seeded start / capacity")
     out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-10, seed=3)

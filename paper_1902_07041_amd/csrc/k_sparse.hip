@@ -189,13 +189,23 @@ __global__ __launch_bounds__(256) void k_cheb_step(
 // rows costs one set of vector loads instead of up to R.  Block values are
 // read in tile order from a running offset, so their scalar loads depend
 // only on the (column, mask) record.
+//
+// The step is evaluated as out_i = alpha acc_i with
+//   acc_i = (delta/alpha) prev_i + (zeta/alpha) add_i        (at tile start)
+//         + sum_j H_ij tin_j + (beta/alpha) tin_i            (record loop)
+// (coefficients cb, cd, cz from the host).  prev and add are read with the
+// tile's records, before the first gather, and the diagonal term uses the
+// T_in row the loop gathers anyway (record flag bit R + r marks row r's own
+// column), so the tile ends with stores only instead of two more serial
+// memory round trips.  alpha == 0 (no matrix term): acc = cb tin + cd prev
+// + cz add at tile start, no record loop, out = acc.
 template <typename T, int VW, int NP, int U, int R>
 __global__ __launch_bounds__(256) void k_cheb_tile(
     int n_atoms, int n_tiles, const int64_t* __restrict__ tile_ptr,
     const int64_t* __restrict__ tile_vptr, const int2* __restrict__ tile_cm,
     const int32_t* __restrict__ tile_row, const T* __restrict__ vals,
     const T* __restrict__ tin, const T* prev, const T* add, T* out, int q, int64_t ld, T alpha,
-    T beta, T delta, T zeta, int chunk) {
+    T cb, T cd, T cz, int chunk) {
   using vt = typename VT<T, VW>::type;
   const int lb = map_block(blockIdx.x, chunk);
   const int wave = uniform(threadIdx.x >> 6);
@@ -203,20 +213,15 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
   const int tile = uniform(lb * kWavesPerBlock + wave);
   if (tile >= n_tiles) return;
   const int col0 = blockIdx.y * (64 * NP * VW);
+  const bool mat = alpha != T(0);
   vt acc[R][3][NP];
   bool act[NP];
   // byte offsets of this lane's columns in the three rows of an atom, so a
-  // gather is one uniform row address plus these (lanes past q read column
-  // col0 of the same rows; their sums are never stored)
+  // row access is one uniform row address plus these (lanes past q read
+  // column col0 of the same rows; their sums are never stored)
   uint32_t boff[3][NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      acc[r][0][p] = vt(0);
-      acc[r][1][p] = vt(0);
-      acc[r][2][p] = vt(0);
-    }
     const int c = col0 + (lane + 64 * p) * VW;
     act[p] = c < q;
     const int64_t e = act[p] ? c : col0;
@@ -225,17 +230,101 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
   }
   const int64_t ld3 = 3 * ld;
   const int64_t ubase = tile_ptr[tile];
-  const int nrec = (alpha != T(0)) ? (int)(tile_ptr[tile + 1] - ubase) : 0;
+  const int nrec = mat ? (int)(tile_ptr[tile + 1] - ubase) : 0;
   const int2* rec = tile_cm + ubase;
   const T* hv = vals + tile_vptr[tile] * 9;
   int rows[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) rows[r] = tile_row[tile * R + r];   // -1: no row
-  // records of the next batch are requested with this batch's block values
-  // (past the tile: the next tile's records or the padding)
+  // records of the first batch, requested with the accumulator start values
   int2 cm[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) cm[u] = rec[u];
+  // One branch-free block per set of streams, so every start value is
+  // requested before the first wait (rows past the last read row 0 and are
+  // never stored).
+  const char* rb[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    rb[r] = reinterpret_cast<const char*>((int64_t)(rows[r] >= 0 ? rows[r] : 0) * ld3 *
+                                          (int64_t)sizeof(T));
+  auto start2 = [&](const T* s1, T c1, const T* s2, T c2) {
+    vt v1[R][3][NP], v2[R][3][NP];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int64_t o = reinterpret_cast<int64_t>(rb[r]) + boff[a][p];
+          v1[r][a][p] = ld_nt(reinterpret_cast<const vt*>(reinterpret_cast<const char*>(s1) + o));
+          v2[r][a][p] = ld_nt(reinterpret_cast<const vt*>(reinterpret_cast<const char*>(s2) + o));
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[r][a][p] = c1 * v1[r][a][p] + c2 * v2[r][a][p];
+  };
+  auto start1 = [&](const T* s1, T c1) {
+    vt v1[R][3][NP];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int64_t o = reinterpret_cast<int64_t>(rb[r]) + boff[a][p];
+          v1[r][a][p] = ld_nt(reinterpret_cast<const vt*>(reinterpret_cast<const char*>(s1) + o));
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[r][a][p] = c1 * v1[r][a][p];
+  };
+  if (!mat && cb != T(0)) {   // no matrix term: tin enters here, not through the loop
+    if (cd != T(0)) {
+      start2(tin, cb, prev, cd);
+      if (cz != T(0)) {
+        vt t[R][3][NP];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+              t[r][a][p] = acc[r][a][p];
+        start1(add, cz);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[r][a][p] += t[r][a][p];
+      }
+    } else if (cz != T(0)) {
+      start2(tin, cb, add, cz);
+    } else {
+      start1(tin, cb);
+    }
+  } else if (cd != T(0) && cz != T(0)) {
+    start2(prev, cd, add, cz);
+  } else if (cd != T(0)) {
+    start1(prev, cd);
+  } else if (cz != T(0)) {
+    start1(add, cz);
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[r][a][p] = vt(0);
+  }
+  __builtin_amdgcn_sched_barrier(0);   // start values in registers before the first gathers
   for (int k = 0; k < nrec; k += U) {
     vt x[U][3][NP];
 #pragma unroll
@@ -248,6 +337,8 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
           for (int a = 0; a < 3; ++a) x[u][a][p] = *reinterpret_cast<const vt*>(rowp + boff[a][p]);
       }
     }
+    // records of the next batch are requested with this batch's block values
+    // (past the tile: the next tile's records or the padding)
     int2 cn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) cn[u] = rec[k + U + u];
@@ -281,18 +372,35 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
                 acc[r][a][p] += h[r][3 * a + 2] * x[u][2][p];
               }
           }
+          if (((m >> (R + r)) & 1) && cb != T(0)) {   // row r's own column: the diagonal shift
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+              for (int a = 0; a < 3; ++a) acc[r][a][p] += cb * x[u][a][p];
+          }
         }
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) cm[u] = cn[u];
   }
+  const T so = mat ? alpha : T(1);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int row = rows[r];
-    if (row >= 0)
-      step_epilogue<T, VW, NP>(acc[r], act, row, lane, col0, tin, prev, add, out, ld, alpha,
-                               beta, delta, zeta);
+    if (rows[r] < 0) continue;
+    char* op = reinterpret_cast<char*>(out) + (int64_t)rows[r] * ld3 * (int64_t)sizeof(T);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      if (!act[p]) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const vt o = so * acc[r][a][p];
+        if (PFE_CHEB_NT_OUT)
+          st_nt(o, reinterpret_cast<vt*>(op + boff[a][p]));
+        else
+          *reinterpret_cast<vt*>(op + boff[a][p]) = o;
+      }
+    }
   }
 }
 
@@ -346,21 +454,22 @@ hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev,
   const int64_t grid_x = ((nblk + 8LL * chunk - 1) / (8LL * chunk)) * 8LL * chunk;
   const int cols_per_group = 64 * NP * VW;
   dim3 grid((unsigned)grid_x, (unsigned)((q + cols_per_group - 1) / cols_per_group));
+  // tile kernels: out = alpha acc, acc started from prev and add scaled by
+  // 1/alpha (quotients rounded once, from the double values)
+  const double sa = alpha != T(0) ? (double)alpha : 1.0;
+  const T cb = (T)((double)beta / sa), cd = (T)((double)delta / sa), cz = (T)((double)zeta / sa);
   if (R == 2) {
     hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 2>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, beta, delta, zeta,
-                       chunk);
+                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, cb, cd, cz, chunk);
   } else if (R == 3) {
     hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 3>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, beta, delta, zeta,
-                       chunk);
+                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, cb, cd, cz, chunk);
   } else if (R == 4) {
     hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 4>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, beta, delta, zeta,
-                       chunk);
+                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, cb, cd, cz, chunk);
   } else {
     hipLaunchKernelGGL((k_cheb_step<T, VW, NP, kUnroll>), grid, dim3(256), 0, s, (int)A.n_atoms,
                        A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, ld, alpha, beta,
@@ -591,6 +700,8 @@ hipError_t validate_masses(int64_t n_atoms, const double* masses, int* err_flags
   return hipGetLastError();
 }
 
+constexpr int64_t kDiagMark = 1LL << 62;   // marks a row's diagonal flag among its blocks
+
 void build_row_tiles(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col_idx, int R,
                      const int32_t* order, std::vector<int64_t>& tile_ptr,
                      std::vector<int64_t>& tile_vptr, std::vector<int32_t>& tile_cm,
@@ -610,16 +721,17 @@ void build_row_tiles(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col
       tile_row[t * R + r] = (int32_t)row;
       for (int64_t b = row_ptr[row]; b < row_ptr[row + 1]; ++b)
         ent.emplace_back(col_idx[b], ((int64_t)r << 40) | b);
+      ent.emplace_back((int32_t)row, kDiagMark | ((int64_t)(R + r) << 40));   // bit R + r
     }
-    std::sort(ent.begin(), ent.end());   // by column, then tile row
+    std::sort(ent.begin(), ent.end());   // by column, then tile row, flags last
     tile_vptr[t] = (int64_t)perm.size();
     int64_t nu = 0;
     for (size_t e = 0; e < ent.size();) {
       const int32_t c = ent[e].first;
       int32_t mask = 0;
       for (; e < ent.size() && ent[e].first == c; ++e) {
-        mask |= 1 << (int)(ent[e].second >> 40);
-        perm.push_back(ent[e].second & ((1LL << 40) - 1));
+        mask |= 1 << (int)((ent[e].second >> 40) & 0xff);
+        if (!(ent[e].second & kDiagMark)) perm.push_back(ent[e].second & ((1LL << 40) - 1));
       }
       tile_cm.push_back(c);
       tile_cm.push_back(mask);

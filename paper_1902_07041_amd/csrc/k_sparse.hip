@@ -7,8 +7,10 @@
 // matrix rows; one atom row when tiles are off).  Lane l owns NP column
 // chunks of VW contiguous elements, chunk = l + 64 p, so a neighbour's three
 // rows of T_in (3 q contiguous elements) are read by coalesced 8-32 byte
-// vector loads.  Tile records (column, row mask) and the block values are
-// wave-uniform and go through scalar loads.  Work-groups are dealt to the
+// vector loads.  A tile's records (column, row mask) arrive with one vector
+// load, a record per lane, and are taken with readlane; the block values are
+// wave-uniform and go through scalar loads, a batch's all at once, so each
+// batch of U records costs one memory round trip.  Work-groups are dealt to the
 // XCDs in chunks sized to the pattern's neighbour span (or one range per XCD
 // for the locality order), so rows that share T_in rows share an L2.
 #include <algorithm>
@@ -188,7 +190,8 @@ __global__ __launch_bounds__(256) void k_cheb_step(
 // that stores block (row, j), so a T_in row shared by neighbouring output
 // rows costs one set of vector loads instead of up to R.  Block values are
 // read in tile order from a running offset, so their scalar loads depend
-// only on the (column, mask) record.
+// only on the (column, mask) records, which sit in the lanes of one vector
+// register (64 per window) and cost no load inside the record loop.
 //
 // The step is evaluated as out_i = alpha acc_i with
 //   acc_i = (delta/alpha) prev_i + (zeta/alpha) add_i        (at tile start)
@@ -206,6 +209,7 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
     const int32_t* __restrict__ tile_row, const T* __restrict__ vals,
     const T* __restrict__ tin, const T* prev, const T* add, T* out, int q, int64_t ld, T alpha,
     T cb, T cd, T cz, int chunk) {
+  static_assert(64 % U == 0, "a record batch must not straddle two 64-record windows");
   using vt = typename VT<T, VW>::type;
   const int lb = map_block(blockIdx.x, chunk);
   const int wave = uniform(threadIdx.x >> 6);
@@ -236,10 +240,15 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
   int rows[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) rows[r] = tile_row[tile * R + r];   // -1: no row
-  // records of the first batch, requested with the accumulator start values
-  int2 cm[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) cm[u] = rec[u];
+  // the tile's records, lane i holding record w + i of the current 64-record
+  // window w (requested with the accumulator start values); the loop takes
+  // them with readlane, so no record load sits in the batch chain
+  int rx = 0, ry = 0;
+  if (lane < nrec) {
+    const int2 v = rec[lane];
+    rx = v.x;
+    ry = v.y;
+  }
   // One branch-free block per set of streams, so every start value is
   // requested before the first wait (rows past the last read row 0 and are
   // never stored).
@@ -326,6 +335,20 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
   }
   __builtin_amdgcn_sched_barrier(0);   // start values in registers before the first gathers
   for (int k = 0; k < nrec; k += U) {
+    if (k > 0 && (k & 63) == 0) {   // next window of 64 records
+      rx = ry = 0;
+      if (k + lane < nrec) {
+        const int2 v = rec[k + lane];
+        rx = v.x;
+        ry = v.y;
+      }
+    }
+    int2 cm[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = (k + u) & 63;   // U divides 64: a batch never straddles two windows
+      cm[u] = make_int2(__builtin_amdgcn_readlane(rx, l), __builtin_amdgcn_readlane(ry, l));
+    }
     vt x[U][3][NP];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -337,29 +360,41 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
           for (int a = 0; a < 3; ++a) x[u][a][p] = *reinterpret_cast<const vt*>(rowp + boff[a][p]);
       }
     }
-    // records of the next batch are requested with this batch's block values
-    // (past the tile: the next tile's records or the padding)
-    int2 cn[U];
+    // Every block of the batch is requested with its gathers, before the
+    // first product: block addresses are branch-free (a row without a block
+    // in a record reads the next block, or the zero padding past the last
+    // tile, and never uses it).
+    T hb[U][R][9];
+    {
+      int o = 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) cn[u] = rec[k + U + u];
+      for (int u = 0; u < U; ++u) {
+        const int m = (u == 0 || k + u < nrec) ? cm[u].y : 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int idx = o + __builtin_popcount(m & ((1 << r) - 1));
+#pragma unroll
+          for (int t = 0; t < 9; ++t) hb[u][r][t] = hv[9 * idx + t];
+        }
+        o += __builtin_popcount(m & ((1 << R) - 1));
+      }
+      hv += 9 * o;
+    }
+    // The empty asm reads every value in a scalar register here, so the
+    // compiler cannot sink a block's load into the branch that uses it (which
+    // would cost one more memory round trip per record).
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) asm volatile("" ::"s"(hb[u][r][t]));
     __builtin_amdgcn_sched_barrier(0);   // keep the request here, ahead of the products
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (u == 0 || k + u < nrec) {
         const int m = cm[u].y;
-        // the record's blocks (consecutive, one per set mask bit) are all
-        // requested before the first product
-        T h[R][9];
-        int nb = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          if ((m >> r) & 1) {
-#pragma unroll
-            for (int t = 0; t < 9; ++t) h[r][t] = hv[9 * nb + t];
-            ++nb;
-          }
-        }
-        hv += 9 * nb;
+        const T (&h)[R][9] = hb[u];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           if ((m >> r) & 1) {
@@ -381,8 +416,6 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
         }
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) cm[u] = cn[u];
   }
   const T so = mat ? alpha : T(1);
 #pragma unroll

@@ -79,8 +79,8 @@ struct Bsr {
   // processing order of the rows.  Tile t owns union columns
   // [tile_ptr[t], tile_ptr[t+1]) of tile_cm, each a (column, row mask) pair
   // (bit r set when row tile_row[t*R + r] stores a block in that column;
-  // bit R + r marks that row's own column, a record without blocks being
-  // added when the row stores no diagonal block), sorted by column.  With tiles active the fused step reads its block
+  // bit R + r marks that row's own column, i.e. its diagonal block, which
+  // every validated pattern stores), sorted by column.  With tiles active the fused step reads its block
   // values in tile order: the blocks of tile t are [tile_vptr[t], tile_vptr[t+1]) and
   // follow (union column, tile row) order.  tile_cm carries kBsrPad padded
   // entries.

@@ -754,7 +754,10 @@ void build_row_tiles(int64_t n_atoms, const int64_t* row_ptr, const int32_t* col
       tile_row[t * R + r] = (int32_t)row;
       for (int64_t b = row_ptr[row]; b < row_ptr[row + 1]; ++b)
         ent.emplace_back(col_idx[b], ((int64_t)r << 40) | b);
-      ent.emplace_back((int32_t)row, kDiagMark | ((int64_t)(R + r) << 40));   // bit R + r
+      // bit R + r on the row's own column (validated patterns store the
+      // diagonal block, so this only flags that record; without one it
+      // would become a record of its own, carrying no block)
+      ent.emplace_back((int32_t)row, kDiagMark | ((int64_t)(R + r) << 40));
     }
     std::sort(ent.begin(), ent.end());   // by column, then tile row, flags last
     tile_vptr[t] = (int64_t)perm.size();

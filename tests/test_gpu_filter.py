@@ -43,9 +43,15 @@ def test_filter_fp64_parity(case, q, d):
 
 
 @pytest.mark.parametrize("q", [1, 8, 96, 160, 256])
-def test_filter_fp32_parity(case, q):
-    banner(f"apply_filter fp32 q={q}")
-    f = design(case, 30)
+@pytest.mark.parametrize("d", [0, 1, 2, 3, 30])
+def test_filter_fp32_parity(case, q, d):
+    """Degrees 0-3 take the special first and last launches (degree 0 has no
+    matrix term at all: Y = g_0 X)."""
+    banner(f"apply_filter fp32 q={q} d={d}")
+    f = design(case, max(d, 1))
+    if d < f.degree:
+        f.coef = f.coef[: d + 1].copy()
+        f.degree = d
     X = gaussian_block(case.n, q, 200 + q)
     Y = P.pfe_apply_filter(case.h, f, X.astype(np.float32))
     ref = chebyshev.apply_filter(case.H, f.c, f.e, f.coef, X)
@@ -244,5 +250,42 @@ def test_filter_tiny_patterns(shape, q):
         Y = P.pfe_apply_filter(h, f, X)
         ref = chebyshev.apply_filter(Hd, f.c, f.e, f.coef, X)
         assert np.abs(Y - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1.0)
+    finally:
+        P.pfe_destroy(h)
+
+
+
+def test_set_hessian_requires_the_diagonal_block():
+    """Every block row must store its diagonal block (the spectral map's shift
+    enters the fused step through it): a 5-atom chain with the diagonal
+    blocks of atoms 0 and 3 left out, and one with an empty sixth row, are
+    both rejected with EINVAL before any filter runs."""
+    from synth.glass import assemble_blocks
+    banner("set_hessian rejects rows without their diagonal block")
+    rng = np.random.default_rng(9)
+    pairs = np.array([(i, i + 1) for i in range(4)], dtype=np.int64)
+    unit = rng.standard_normal((4, 3))
+    unit /= np.linalg.norm(unit, axis=1, keepdims=True)
+    row_ptr5, col_idx5, blocks5 = assemble_blocks(5, pairs, unit, rng.uniform(0.5, 1.5, 4))
+    keep = np.ones(col_idx5.size, dtype=bool)
+    for i in (0, 3):
+        for b in range(row_ptr5[i], row_ptr5[i + 1]):
+            keep[b] &= col_idx5[b] != i
+    rows = np.repeat(np.arange(5), np.diff(row_ptr5))[keep]
+    row_ptr = np.zeros(6, dtype=np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    masses = rng.uniform(60.0, 90.0, 6)
+    h = P.pfe_create(0)
+    try:
+        with pytest.raises(P.PfeError) as e:      # diagonal blocks of atoms 0 and 3 missing
+            P.pfe_set_hessian(h, row_ptr, col_idx5[keep].astype(np.int32), blocks5[keep],
+                              masses[:5])
+        assert e.value.status == -1
+        empty = np.append(row_ptr5, row_ptr5[-1])   # a sixth atom without any block
+        with pytest.raises(P.PfeError) as e:
+            P.pfe_set_hessian(h, empty, col_idx5, blocks5, masses)
+        assert e.value.status == -1
+        P.pfe_set_hessian(h, row_ptr5, col_idx5, blocks5, masses[:5])   # the full chain loads
     finally:
         P.pfe_destroy(h)

@@ -8,6 +8,9 @@
 // neighbour, a 3x3 matrix of dot products over the q columns reduced across
 // the wave.  Every block is written only by the wave of its row, so the
 // accumulation needs no atomics and is deterministic.
+#include <algorithm>
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace pfe {
@@ -133,6 +136,17 @@ __global__ __launch_bounds__(256) void k_sddmm_seg(int n_atoms, const int64_t* _
 // q <= 64 and m <= MM: the wave's own three rows of every a_m (with w_m
 // folded in) stay in registers across the row's blocks, so a block loads
 // only its neighbour's rows; same products and order as k_sddmm_seg.
+//
+// Work-groups are dealt to the XCDs in chunks of `chunk` (work-group b runs on
+// XCD b % 8; chunk c of consecutive rows goes to XCD c % 8), as in the fused
+// filter step: with eight chunks spanning the pattern's typical neighbour
+// offset, a row and its neighbours one lattice plane away share an L2, so
+// their gathered rows of T are fetched from memory once per XCD.
+__device__ __forceinline__ int xcd_chunk_row_group(int b, int chunk) {
+  const int xcd = b & 7, s = b >> 3;
+  return ((s / chunk) * 8 + xcd) * chunk + (s % chunk);
+}
+
 template <int MM>
 __global__ __launch_bounds__(256) void k_sddmm_seg_reg(int n_atoms, const int64_t* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col_idx, int q,
@@ -140,10 +154,11 @@ __global__ __launch_bounds__(256) void k_sddmm_seg_reg(int n_atoms, const int64_
                                                        int64_t a_stride,
                                                        const double* __restrict__ T,
                                                        int64_t t_stride, int64_t ld,
-                                                       const double* __restrict__ w, double* G) {
+                                                       const double* __restrict__ w, double* G,
+                                                       int chunk) {
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int row = uniform(blockIdx.x * 4 + wave);
+  const int row = uniform(xcd_chunk_row_group(blockIdx.x, chunk) * 4 + wave);
   if (row >= n_atoms) return;
   const bool act = lane < q;
   const int c = act ? lane : 0;
@@ -361,17 +376,38 @@ hipError_t assemble_springs(int64_t n_atoms, const int64_t* row_ptr, const int32
   return hipGetLastError();
 }
 
-constexpr int kSegRegMax = 16;   // checkpoint segments up to 16 steps (degree <= 256)
+// Register-resident segment kernels for segments of up to 8, 13 and 16
+// steps (the default stride ceil(sqrt(d)) for d <= 64, 169, 256): the rows
+// of a_m take 6 VGPRs per step, so the smallest fit keeps the most waves
+// (96, 126 and 144 VGPRs: 5, 4 and 3 waves per SIMD).
+constexpr int kSegRegMax = 16;
 
 hipError_t sddmm_seg_f64(const Bsr& A, int q, int m, const double* a, int64_t a_stride,
                          const double* t, int64_t t_stride, int64_t ld, const double* w,
                          double* G, hipStream_t s) {
   if (A.n_atoms == 0 || m == 0) return hipSuccess;
   const unsigned grid = nb(A.n_atoms, 4);
-  if (q <= 64 && m <= kSegRegMax)
-    hipLaunchKernelGGL(k_sddmm_seg_reg<kSegRegMax>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms,
-                       A.row_ptr, A.col_idx, q, m, a, a_stride, t, t_stride, ld, w, G);
-  else if (q <= 64)
+  if (q <= 64 && m <= kSegRegMax) {
+    // chunks of work-groups (4 rows each), eight of them spanning the
+    // pattern's neighbour span; the grid is padded to whole rounds of 8 chunks
+    const int64_t per_xcd = ((int64_t)grid + 7) / 8;
+    int64_t chunk = A.span > 0 ? std::max<int64_t>(1, (A.span + 16) / 32) : 1;
+    const char* e = std::getenv("PFEIG_SDDMM_CHUNK");
+    if (e) chunk = std::max(1, std::atoi(e));
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(per_xcd, 1));
+    const int64_t gridp = (((int64_t)grid + 8 * chunk - 1) / (8 * chunk)) * 8 * chunk;
+#define PFE_SEG_REG(MM_)                                                                       \
+  hipLaunchKernelGGL(k_sddmm_seg_reg<MM_>, dim3((unsigned)gridp), dim3(256), 0, s,               \
+                     (int)A.n_atoms, A.row_ptr, A.col_idx, q, m, a, a_stride, t, t_stride, ld, w, \
+                     G, (int)chunk)
+    if (m <= 8)
+      PFE_SEG_REG(8);
+    else if (m <= 13)
+      PFE_SEG_REG(13);
+    else
+      PFE_SEG_REG(kSegRegMax);
+#undef PFE_SEG_REG
+  } else if (q <= 64)
     hipLaunchKernelGGL(k_sddmm_seg<1>, dim3(grid), dim3(256), 0, s, (int)A.n_atoms, A.row_ptr,
                        A.col_idx, q, m, a, a_stride, t, t_stride, ld, w, G);
   else if (q <= 128)

@@ -24,8 +24,13 @@ def tiny():
 
 
 @pytest.mark.parametrize("d,stride,q", [(12, 0, 3), (12, 5, 3), (1, 0, 2), (0, 0, 2), (31, 4, 64),
-                                        (7, 1, 70)])
+                                        (7, 1, 70), (60, 10, 64), (150, 0, 16), (200, 0, 8)])
 def test_adjoint_parity(tiny, d, stride, q):
+    """Segments of the checkpointed reverse sweep hold `stride` steps
+    (ceil(sqrt d) by default): up to 5 here with the first five cases, 10
+    and 13 (d = 150, the benchmark's degree) and 15 (d = 200) with the last
+    three, so every register-resident segment kernel (8, 13 and 16 steps)
+    and the q > 64 path are compared with the oracle."""
     banner(f"adjoint d={d} stride={stride} q={q}")
     c, e = F.spectral_map(0.0, tiny.ub)
     xi, eta = (0.05 * tiny.lam[-1] - c) / e, (0.15 * tiny.lam[-1] - c) / e

@@ -120,14 +120,15 @@ template <typename T, int VW, int NP, int U>
 __global__ __launch_bounds__(256) void k_cheb_step(
     int n_atoms, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const T* __restrict__ vals, const T* __restrict__ tin, const T* prev, const T* add, T* out,
-    int q, int64_t ld, T alpha, T beta, T delta, T zeta, int chunk) {
+    int q, int pass_w, int64_t ld, T alpha, T beta, T delta, T zeta, int chunk) {
   using vt = typename VT<T, VW>::type;
   const int lb = map_block(blockIdx.x, chunk);
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int row = uniform(lb * kWavesPerBlock + wave);
   if (row >= n_atoms) return;
-  const int col0 = blockIdx.y * (64 * NP * VW);
+  const int col0 = blockIdx.y * pass_w;
+  const int cend = min(q, col0 + pass_w);
 
   vt acc[3][NP];
   bool act[NP];
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(256) void k_cheb_step(
     acc[0][p] = vt(0);
     acc[1][p] = vt(0);
     acc[2][p] = vt(0);
-    act[p] = col0 + (lane + 64 * p) * VW < q;
+    act[p] = col0 + (lane + 64 * p) * VW < cend;
   }
   const int64_t b0 = row_ptr[row];
   const int64_t b1 = (alpha != T(0)) ? row_ptr[row + 1] : b0;
@@ -207,8 +208,8 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
     int n_atoms, int n_tiles, const int64_t* __restrict__ tile_ptr,
     const int64_t* __restrict__ tile_vptr, const int2* __restrict__ tile_cm,
     const int32_t* __restrict__ tile_row, const T* __restrict__ vals,
-    const T* __restrict__ tin, const T* prev, const T* add, T* out, int q, int64_t ld, T alpha,
-    T cb, T cd, T cz, int chunk) {
+    const T* __restrict__ tin, const T* prev, const T* add, T* out, int q, int pass_w,
+    int64_t ld, T alpha, T cb, T cd, T cz, int chunk) {
   static_assert(64 % U == 0, "a record batch must not straddle two 64-record windows");
   using vt = typename VT<T, VW>::type;
   const int lb = map_block(blockIdx.x, chunk);
@@ -216,7 +217,8 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
   const int lane = threadIdx.x & 63;
   const int tile = uniform(lb * kWavesPerBlock + wave);
   if (tile >= n_tiles) return;
-  const int col0 = blockIdx.y * (64 * NP * VW);
+  const int col0 = blockIdx.y * pass_w;   // this pass: columns [col0, min(q, col0 + pass_w))
+  const int cend = min(q, col0 + pass_w);
   const bool mat = alpha != T(0);
   vt acc[R][3][NP];
   bool act[NP];
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     const int c = col0 + (lane + 64 * p) * VW;
-    act[p] = c < q;
+    act[p] = c < cend;
     const int64_t e = act[p] ? c : col0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) boff[a][p] = (uint32_t)((a * ld + e) * (int64_t)sizeof(T));
@@ -462,8 +464,8 @@ int chunk_override() { return env_int("PFEIG_CHEB_CHUNK", -1); }
 
 template <typename T, int VW, int NP>
 hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, const T* add,
-                       T* out, int q, int64_t ld, T alpha, T beta, T delta, T zeta,
-                       hipStream_t s) {
+                       T* out, int q, int pass_w, int64_t ld, T alpha, T beta, T delta,
+                       T zeta, hipStream_t s) {
   const int R = (A.tile_rows >= 2 && A.tile_ptr) ? A.tile_rows : 1;   // vals in tile order
   if (R >= 2 && (3 * ld) * (int64_t)sizeof(T) > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
   const int64_t units = (R >= 2) ? A.n_tiles : A.n_atoms;   // one wave per unit
@@ -485,8 +487,8 @@ hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev,
   if (chunk_override() >= 0) chunk = chunk_override();         // work-groups, as given
   if (chunk <= 0 || chunk > per_xcd) chunk = (int)per_xcd;
   const int64_t grid_x = ((nblk + 8LL * chunk - 1) / (8LL * chunk)) * 8LL * chunk;
-  const int cols_per_group = 64 * NP * VW;
-  dim3 grid((unsigned)grid_x, (unsigned)((q + cols_per_group - 1) / cols_per_group));
+  if (pass_w <= 0 || pass_w > 64 * NP * VW || pass_w % VW) return hipErrorInvalidValue;
+  dim3 grid((unsigned)grid_x, (unsigned)((q + pass_w - 1) / pass_w));
   // tile kernels: out = alpha acc, acc started from prev and add scaled by
   // 1/alpha (quotients rounded once, from the double values)
   const double sa = alpha != T(0) ? (double)alpha : 1.0;
@@ -494,19 +496,22 @@ hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev,
   if (R == 2) {
     hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 2>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, cb, cd, cz, chunk);
+                       A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
+                       chunk);
   } else if (R == 3) {
     hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 3>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, cb, cd, cz, chunk);
+                       A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
+                       chunk);
   } else if (R == 4) {
     hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 4>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                       A.tile_row, vals, tin, prev, add, out, q, ld, alpha, cb, cd, cz, chunk);
+                       A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
+                       chunk);
   } else {
     hipLaunchKernelGGL((k_cheb_step<T, VW, NP, kUnroll>), grid, dim3(256), 0, s, (int)A.n_atoms,
-                       A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, ld, alpha, beta,
-                       delta, zeta, chunk);
+                       A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, pass_w, ld, alpha,
+                       beta, delta, zeta, chunk);
   }
   return hipGetLastError();
 }
@@ -540,22 +545,30 @@ hipError_t dispatch_cheb(const Bsr& A, const T* vals, const T* tin, const T* pre
   while (vw > 1 && !fits(vw)) vw /= 2;
   const int chunks = (q + vw - 1) / vw;
   int np = chunks <= 64 ? 1 : (chunks <= 128 ? 2 : 4);
-  // Columns per pass (blockIdx.y takes the rest).  FP64 beyond 192 columns
-  // runs 128-column passes (VW 2, 8 waves per SIMD) instead of one VW-4 pass
-  // (126 VGPRs, 4 waves): q = 256 on the 1e6-atom glass 8.79 -> 7.58 ms per
-  // step, although the matrix is read once per pass; at q = 160 (a second
-  // pass of 32 columns) and in FP32 one pass measured faster.
-  // PFEIG_CHEB_PASS_COLS overrides.
+  // Column passes (blockIdx.y): with a limit of `lim` columns the q columns
+  // are split into ceil(q / lim) passes of equal width, each on the narrowest
+  // lane layout that covers it.  FP64 beyond 128 columns runs passes of at
+  // most 128 columns (VW 2, 8 waves per SIMD) instead of one VW-4 pass (4
+  // waves), although the matrix is read once per pass: on the 1e6-atom glass
+  // q = 256 8.79 -> 7.58 ms per step (two 128-column passes) and q = 160
+  // 5.12 -> 4.84 ms (two of 80); in FP32 one pass measured faster (q = 160:
+  // 2.32 against 3.72 ms).  PFEIG_CHEB_PASS_COLS overrides.
   int lim = pass_cols_override();
-  if (lim <= 0 && sizeof(T) == 8 && q > 192) lim = 128;
-  if (lim > 0) {
-    while (np > 1 && 64 * np * vw > lim) np /= 2;
-    while (vw > 1 && 64 * np * vw > lim && fits(vw / 2)) vw /= 2;
+  if (lim <= 0 && sizeof(T) == 8 && q > 128) lim = 128;
+  int pass_w = 64 * np * vw;
+  if (lim > 0 && lim < q) {
+    const int npass = (q + lim - 1) / lim;
+    const int pw = (q + npass - 1) / npass;
+    while (np > 1 && 64 * (np / 2) * vw >= pw) np /= 2;
+    while (vw > 1 && 64 * np * (vw / 2) >= pw && fits(vw / 2)) vw /= 2;
+    pass_w = std::min(64 * np * vw, ((pw + vw - 1) / vw) * vw);
+  } else {
+    pass_w = std::min(pass_w, ((q + vw - 1) / vw) * vw);
   }
 #define PFE_CHEB_CASE(VW_, NP_)                                                               \
   if (vw == VW_ && np == NP_)                                                                 \
-    return launch_cheb<T, VW_, NP_>(A, vals, tin, prev, add, out, q, ld, alpha, beta, delta,  \
-                                    zeta, s);
+    return launch_cheb<T, VW_, NP_>(A, vals, tin, prev, add, out, q, pass_w, ld, alpha, beta, \
+                                    delta, zeta, s);
   PFE_CHEB_CASE(1, 1)
   PFE_CHEB_CASE(1, 2)
   PFE_CHEB_CASE(1, 4)

@@ -201,7 +201,7 @@ def test_device_inputs_ordered_after_torch_default_stream(case):
         P.pfe_destroy(h)
 
 
-@pytest.mark.parametrize("q", [96, 256])
+@pytest.mark.parametrize("q", [96, 160, 256])
 def test_filter_schedule_does_not_change_bits(case, q, monkeypatch):
     """Work-groups per XCD chunk and columns per pass only change which wave
     computes a row when: every output element sums its blocks in the same
@@ -210,8 +210,10 @@ def test_filter_schedule_does_not_change_bits(case, q, monkeypatch):
     f = design(case, 25)
     X = gaussian_block(case.n, q, 41)
     out = []
+    # column limits: 64 and 128 give equal passes (q = 160: 3 x 54 or 2 x 80),
+    # 1024 a single pass on the widest lane layout
     for chunk, cols in [(None, None), ("1", None), ("7", None), ("100000", None), (None, "64"),
-                        (None, "128")]:
+                        (None, "128"), (None, "1024")]:
         for name, val in (("PFEIG_CHEB_CHUNK", chunk), ("PFEIG_CHEB_PASS_COLS", cols)):
             if val is None:
                 monkeypatch.delenv(name, raising=False)

@@ -291,3 +291,49 @@ def test_set_hessian_requires_the_diagonal_block():
         P.pfe_set_hessian(h, row_ptr5, col_idx5, blocks5, masses[:5])   # the full chain loads
     finally:
         P.pfe_destroy(h)
+
+
+@pytest.fixture(scope="module")
+def dense_cluster():
+    """80 atoms with a spring between every pair: 80 blocks per row, so a row
+    tile carries more than 64 (column, mask) records."""
+    from synth.glass import assemble_blocks
+    N = 80
+    rng = np.random.default_rng(12)
+    pairs = np.array([(i, j) for i in range(N) for j in range(i + 1, N)], dtype=np.int64)
+    unit = rng.standard_normal((pairs.shape[0], 3))
+    unit /= np.linalg.norm(unit, axis=1, keepdims=True)
+    k = rng.uniform(0.5, 1.5, pairs.shape[0])
+    masses = rng.uniform(60.0, 90.0, N)
+    row_ptr, col_idx, blocks = assemble_blocks(N, pairs, unit, k)
+    Hd = hessian.to_dense(row_ptr, col_idx, hessian.weight_blocks(row_ptr, col_idx, blocks, masses))
+    ub = 1.01 * np.linalg.eigvalsh(Hd)[-1]
+    return row_ptr, col_idx, blocks, masses, Hd, ub
+
+
+@pytest.mark.parametrize("tile_rows", ["2", "4"])
+def test_filter_rows_with_more_than_64_records(dense_cluster, tile_rows, monkeypatch):
+    """Tiles whose records fill more than one 64-lane window: FP64 and FP32
+    filter and the adjoint (block gradient) against the oracle."""
+    from oracle import adjoint
+    banner(f"apply_filter / adjoint, 80 blocks per row, tile_rows={tile_rows}")
+    monkeypatch.setenv("PFEIG_TILE_ROWS", tile_rows)
+    row_ptr, col_idx, blocks, masses, Hd, ub = dense_cluster
+    h = P.pfe_create(0)
+    try:
+        P.pfe_set_hessian(h, row_ptr, col_idx, blocks, masses)
+        P.pfe_set_bounds(h, 0.0, ub)
+        f = P.pfe_design_filter(0.2 * ub, 0.4 * ub, 0.0, ub, degree=20)
+        X = gaussian_block(240, 5, 31)
+        ref = chebyshev.apply_filter(Hd, f.c, f.e, f.coef, X)
+        Y = P.pfe_apply_filter(h, f, X)
+        assert rel_err(Y, ref) < 1e-12
+        Y32 = P.pfe_apply_filter(h, f, X.astype(np.float32))
+        assert rel_err(Y32, ref) < 5e-5
+        W = gaussian_block(240, 5, 32)
+        dX, dB = P.pfe_apply_filter_adjoint(h, f, X, W, int(row_ptr[-1]), 0)
+        rX, rG = adjoint.filter_vjp_blocks(Hd, row_ptr, col_idx, f.c, f.e, f.coef, X, W)
+        assert rel_err(dX, rX) < 1e-12
+        assert rel_err(dB, rG) < 1e-11
+    finally:
+        P.pfe_destroy(h)

@@ -176,8 +176,13 @@ pfe_status pfe_apply_filter(pfe_handle h, const pfe_filter* f, int32_t nvec, con
  * returns dX = dL/dX ([n][ld]) and dblocks = dL/dH on every stored block
  * ([nnzb][3][3], each stored block an independent parameter, c and e held
  * constant), by the adjoint recurrence a_k = g_k dY + 2 H_hat a_{k+1} - a_{k+2},
- * with the forward recurrence vectors recomputed from checkpoints kept every
- * ckpt_stride steps (0: ceil(sqrt(d))). */
+ * over segments of ckpt_stride steps (0: ceil(sqrt(d))), each segment's block
+ * gradient formed in one batched pass.  ckpt_stride > 0: the forward
+ * recurrence vectors of a segment are recomputed from a checkpoint pair kept
+ * per segment (2 ceil(d/s) + s vectors of workspace).  ckpt_stride = 0: all d
+ * forward vectors are kept instead when they fit in half the free device
+ * memory (no recomputation; the library holds that workspace until
+ * pfe_destroy), checkpoints otherwise; both give identical results. */
 pfe_status pfe_apply_filter_adjoint(pfe_handle h, const pfe_filter* f, int32_t nvec,
                                     const double* X, const double* dY, double* dX,
                                     double* dblocks, int64_t ld, int32_t ckpt_stride,

@@ -1934,12 +1934,27 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
   const int nseg = d > 0 ? (d + s - 1) / s : 0;
   const size_t mv = (size_t)n * ld * sizeof(double);
   const int64_t nel = n * ld;
-  // device: X, Ybar, a0/a1 pair, segment buffer (s vectors), checkpoints (2 per segment)
+  // With the stride left to the library, the whole forward trajectory (t_k
+  // for k < d) stays on the device when it fits in half the free memory
+  // (plus what its buffer already holds): no checkpoint copies and no
+  // recomputation.  Segments keep length s for the block gradient, so the
+  // results are bit-identical to the checkpointed sweep.
+  bool keep = false;
+  if (stride <= 0 && d >= 2) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) keep = mv * (size_t)d <= fr / 2 + h->wsCk.bytes;
+  }
+  // device: X, Ybar, a0/a1 pair, adjoint vectors of one segment, and either
+  // the trajectory or a segment buffer (s vectors) and checkpoints (2 per segment)
   PFE_HIP(h->wsA.ensure(mv * 2));                 // X, Ybar (device copies when host inputs)
   PFE_HIP(h->wsB.ensure(mv * (size_t)(s + 2)));  // adjoint vectors of one segment
   PFE_HIP(h->wsSmall.ensure((size_t)std::max(d, 1) * sizeof(double) + 64));
-  PFE_HIP(h->wsC.ensure(mv * (size_t)std::max(s, 1)));
-  PFE_HIP(h->wsCk.ensure(mv * (size_t)std::max(2 * nseg, 1)));
+  if (keep) {
+    PFE_HIP(h->wsCk.ensure(mv * (size_t)d));
+  } else {
+    PFE_HIP(h->wsC.ensure(mv * (size_t)std::max(s, 1)));
+    PFE_HIP(h->wsCk.ensure(mv * (size_t)std::max(2 * nseg, 1)));
+  }
   PFE_HIP(h->wsD.ensure((size_t)(h->nnzb + 1) * 9 * sizeof(double)));
   const double* Xd = X;
   const double* Yb = dY;
@@ -1961,8 +1976,15 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
     return pfe::cheb_step_f64(A, Hs, tin, prev, nullptr, out, nvec, ld, first ? a1 : a2,
                               first ? b1 : b2, first ? 0.0 : -1.0, 0.0, h->stream);
   };
-  // forward sweep storing (t_{js}, t_{js+1}) for every segment j
-  if (d >= 1) {
+  double* traj = h->wsCk.as<double>();   // trajectory: t_k in slot k
+  if (keep) {
+    PFE_HIP(pfe::copy_cols_f64(n, (int)ld, Xd, ld, traj, ld, h->stream));
+    PFE_HIP(fwd(traj, nullptr, traj + nel, true));   // t_1
+    for (int k = 1; k <= d - 2; ++k)
+      PFE_HIP(fwd(traj + (size_t)k * nel, traj + (size_t)(k - 1) * nel, traj + (size_t)(k + 1) * nel,
+                  false));
+  } else if (d >= 1) {
+    // forward sweep storing (t_{js}, t_{js+1}) for every segment j
     double* t_prev = seg;                         // rolling pair in seg[0], seg[1] (s >= 1)
     double* t_cur = (s >= 2) ? seg + nel : aA;
     PFE_HIP(pfe::copy_cols_f64(n, (int)ld, Xd, ld, t_prev, ld, h->stream));
@@ -2013,14 +2035,17 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
       PFE_HIP(pfe::copy_cols_f64(n, (int)ld, segA + nel, ld, segA + (size_t)(w1 + 1) * nel, ld, h->stream));
       PFE_HIP(pfe::copy_cols_f64(n, (int)ld, segA, ld, segA + (size_t)w1 * nel, ld, h->stream));
     }
-    // regenerate t_{k0} .. t_{k1-1} into seg[0 .. k1-k0-1]
-    PFE_HIP(pfe::copy_cols_f64(n, (int)ld, ck + (2 * j) * nel, ld, seg, ld, h->stream));
-    if (w1 >= 2)
-      PFE_HIP(pfe::copy_cols_f64(n, (int)ld, ck + (2 * j + 1) * nel, ld, seg + nel, ld, h->stream));
-    for (int k = k0 + 2; k < k1; ++k)
-      PFE_HIP(pfe::cheb_step_f64(A, Hs, seg + (k - 1 - k0) * nel, seg + (k - 2 - k0) * nel,
-                                 nullptr, seg + (k - k0) * nel, nvec, ld, a2, b2, -1.0, 0.0,
-                                 h->stream));
+    // t_{k0} .. t_{k1-1}: in the trajectory, or regenerated into seg[0 .. k1-k0-1]
+    const double* segT = keep ? traj + (size_t)k0 * nel : seg;
+    if (!keep) {
+      PFE_HIP(pfe::copy_cols_f64(n, (int)ld, ck + (2 * j) * nel, ld, seg, ld, h->stream));
+      if (w1 >= 2)
+        PFE_HIP(pfe::copy_cols_f64(n, (int)ld, ck + (2 * j + 1) * nel, ld, seg + nel, ld, h->stream));
+      for (int k = k0 + 2; k < k1; ++k)
+        PFE_HIP(pfe::cheb_step_f64(A, Hs, seg + (k - 1 - k0) * nel, seg + (k - 2 - k0) * nel,
+                                   nullptr, seg + (k - k0) * nel, nvec, ld, a2, b2, -1.0, 0.0,
+                                   h->stream));
+    }
     for (int k = k1 - 1; k >= k0; --k) {
       const bool last = (k == 0);
       PFE_HIP(pfe::cheb_step_f64(A, Hs, segA + (size_t)(k + 1 - k0) * nel,
@@ -2028,7 +2053,7 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
                                  nvec, ld, last ? a1 : a2, last ? b1 : b2, -1.0, f->coef[k],
                                  h->stream));
     }
-    PFE_HIP(pfe::sddmm_seg_f64(A, nvec, w1, segA + nel, nel, seg, nel, ld, wdev + k0, G, h->stream));
+    PFE_HIP(pfe::sddmm_seg_f64(A, nvec, w1, segA + nel, nel, segT, nel, ld, wdev + k0, G, h->stream));
   }
   double* a_mid = segA;   // a_0 (or g_0 Ybar when d == 0)
   PFE_HIP(pfe::scale_f64(h->nnzb * 9, 1.0 / e, G, h->stream));

@@ -47,6 +47,24 @@ def test_adjoint_parity(tiny, d, stride, q):
         assert np.all(dB == 0)
 
 
+def test_adjoint_trajectory_equals_checkpoints(tiny):
+    """Stride 0 keeps the whole forward trajectory when it fits (it does at
+    this size); an explicit stride of the same ceil(sqrt d) recomputes each
+    segment from checkpoints.  Same segments, same kernels: identical bits."""
+    banner("adjoint, trajectory kept vs checkpoints, d=150")
+    c, e = F.spectral_map(0.0, tiny.ub)
+    xi, eta = (0.05 * tiny.lam[-1] - c) / e, (0.15 * tiny.lam[-1] - c) / e
+    d = 150
+    coef = F.filter_coefficients(xi, eta, 0.05, d, F.NONE)
+    f = P.Filter(d, 0, c, e, xi, eta, 0.05, coef)
+    X = gaussian_block(tiny.n, 16, 23)
+    W = gaussian_block(tiny.n, 16, 24)
+    dX0, dB0 = P.pfe_apply_filter_adjoint(tiny.h, f, X, W, tiny.g.nnzb, 0)
+    dX1, dB1 = P.pfe_apply_filter_adjoint(tiny.h, f, X, W, tiny.g.nnzb, 13)
+    np.testing.assert_array_equal(dX0, dX1)
+    np.testing.assert_array_equal(dB0, dB1)
+
+
 def test_hellmann_feynman_and_chain_rule(tiny):
     banner("eigvec block gradient + spring chain rule")
     g = tiny.g

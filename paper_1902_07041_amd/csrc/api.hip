@@ -40,6 +40,13 @@ struct pfe_ctx {
   int tiled_mode = -1;        // order requested when the tiles were built
   int64_t tiled_span = 0;     // neighbour_span of the pattern
   double h32_c = NAN, h32_e = NAN;
+  // Row tiles of the FP32 filter when its tile height differs from the FP64
+  // one (same pattern and order; built at the first FP32 filter, kept while
+  // the pattern stays): H32 is stored in their order.
+  int tile32_rows = 0;
+  int64_t n_tiles32 = 0;
+  DevBuf t32_ptr, t32_vptr, t32_cm, t32_row, t32_perm;
+  int h32_R = 0;              // tile height H32's order was made for
   // bounds
   bool has_bounds = false;
   double lam_lb = 0, lam_ub = 0;
@@ -68,6 +75,28 @@ struct pfe_ctx {
     a.tile_local = tiled_local;
     a.span = tiled_span;
     return a;
+  }
+  // The pattern as the FP32 filter walks it: its own row tiles when built.
+  pfe::Bsr bsr32() const {
+    pfe::Bsr a = bsr();
+    if (tile32_rows >= 2) {
+      a.tile_rows = tile32_rows;
+      a.n_tiles = n_tiles32;
+      a.tile_ptr = t32_ptr.as<int64_t>();
+      a.tile_vptr = t32_vptr.as<int64_t>();
+      a.tile_cm = t32_cm.as<int2>();
+      a.tile_row = t32_row.as<int32_t>();
+    }
+    return a;
+  }
+  void release_tiles32() {
+    tile32_rows = 0;
+    n_tiles32 = 0;
+    t32_ptr.release();
+    t32_vptr.release();
+    t32_cm.release();
+    t32_row.release();
+    t32_perm.release();
   }
   // Block values as the fused step reads them (tile order when tiles are on).
   const double* step_vals64() const {
@@ -135,6 +164,11 @@ int64_t round_up(int64_t v, int64_t m) { return ((v + m - 1) / m) * m; }
 #define PFE_TILE_ROWS 2
 #endif
 constexpr int kDefaultTileRows = PFE_TILE_ROWS;
+// FP32 filter: three-row tiles keep 8 waves per SIMD (50 VGPRs) and measured
+// 4 % (1e5 atoms) and 8 % (1e6) faster steps at q = 96 than two-row ones,
+// which FP64 keeps (three rows need 92 VGPRs there).  PFEIG_TILE_ROWS_F32
+// overrides.
+constexpr int kDefaultTileRowsF32 = 3;
 // Locality order of the row tiles: rows per leaf range of the bisection
 // (best of 16..1024 in a per-XCD L2 model); a window of rows of the order of
 // what the 256 MB Infinity Cache holds of T_in at q = 96 in FP64 (2304 B per
@@ -196,7 +230,7 @@ struct Timer {
 template <typename T>
 Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double a1, double b1,
                const T* X, T* P, T* Q, int q, int64_t ld, int64_t* steps) {
-  const pfe::Bsr A = h->bsr();
+  const pfe::Bsr A = sizeof(T) == 4 ? h->bsr32() : h->bsr();
   auto step = [&](const T* tin, const T* prev, T* out, double al, double be, double de,
                   double ze) -> hipError_t {
     if constexpr (sizeof(T) == 8)
@@ -241,17 +275,54 @@ Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double
   return pfe::ok();
 }
 
+// FP32 row tiles of height R32 over the FP64 tiles' pattern and order.
+Err ensure_tiles32(pfe_handle h) {
+  int R32 = kDefaultTileRowsF32;
+  if (const char* v = std::getenv("PFEIG_TILE_ROWS_F32")) R32 = std::atoi(v);
+  if (h->tile_rows < 2 || R32 < 2 || R32 > 4 || R32 == h->tile_rows) {
+    h->release_tiles32();   // the FP32 filter walks the FP64 tiles
+    return pfe::ok();
+  }
+  if (h->tile32_rows == R32) return pfe::ok();
+  h->release_tiles32();
+  const int64_t na = h->n_atoms;
+  std::vector<int32_t> order;
+  if (h->tiled_local)
+    pfe::locality_order(na, h->tiled_rp.data(), h->tiled_ci.data(), kOrderLeaf, R32, order);
+  std::vector<int64_t> tp, tv, perm;
+  std::vector<int32_t> tcm, trow;
+  pfe::build_row_tiles(na, h->tiled_rp.data(), h->tiled_ci.data(), R32,
+                       h->tiled_local ? order.data() : nullptr, tp, tv, tcm, trow, perm);
+  PFE_HIP(h->t32_ptr.ensure(tp.size() * sizeof(int64_t)));
+  PFE_HIP(h->t32_vptr.ensure(tv.size() * sizeof(int64_t)));
+  PFE_HIP(h->t32_cm.ensure(tcm.size() * sizeof(int32_t)));
+  PFE_HIP(h->t32_row.ensure(trow.size() * sizeof(int32_t)));
+  PFE_HIP(h->t32_perm.ensure(perm.size() * sizeof(int64_t)));
+  PFE_HIP(hipMemcpy(h->t32_ptr.p, tp.data(), tp.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  PFE_HIP(hipMemcpy(h->t32_vptr.p, tv.data(), tv.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  PFE_HIP(hipMemcpy(h->t32_cm.p, tcm.data(), tcm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  PFE_HIP(hipMemcpy(h->t32_row.p, trow.data(), trow.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  PFE_HIP(hipMemcpy(h->t32_perm.p, perm.data(), perm.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  h->n_tiles32 = (int64_t)tp.size() - 1;
+  h->tile32_rows = R32;
+  return pfe::ok();
+}
+
 Err ensure_h32(pfe_handle h, double c, double e) {
-  if (h->H32.p && h->h32_c == c && h->h32_e == e) return pfe::ok();
+  PFE_TRY(ensure_tiles32(h));
+  const int R32 = h->tile32_rows >= 2 ? h->tile32_rows : h->tile_rows;
+  if (h->H32.p && h->h32_c == c && h->h32_e == e && h->h32_R == R32) return pfe::ok();
   const int64_t nel = (h->nnzb + pfe::kBsrPad) * 9;
   PFE_HIP(h->H32.ensure((size_t)nel * sizeof(float)));
   PFE_HIP(pfe::zero_f32(h->H32.as<float>(), nel, h->stream));
   if (h->tile_rows >= 2) {
-    // formed in row order (diagonal blocks known there), then put in tile order
+    // formed in row order (diagonal blocks known there), then put in the
+    // order of the tiles the FP32 filter walks
+    const DevBuf& perm = h->tile32_rows >= 2 ? h->t32_perm : h->tile_perm;
     PFE_HIP(h->H32row.ensure((size_t)nel * sizeof(float)));
     PFE_HIP(pfe::shift_scale_to_f32(h->bsr(), h->H.as<double>(), c, e, h->H32row.as<float>(),
                                     h->stream));
-    PFE_HIP(pfe::permute_blocks_f32(h->nnzb, h->tile_perm.as<int64_t>(), h->H32row.as<float>(),
+    PFE_HIP(pfe::permute_blocks_f32(h->nnzb, perm.as<int64_t>(), h->H32row.as<float>(),
                                     h->H32.as<float>(), h->stream));
     PFE_HIP(hipStreamSynchronize(h->stream));
     h->H32row.release();
@@ -261,6 +332,7 @@ Err ensure_h32(pfe_handle h, double c, double e) {
   }
   h->h32_c = c;
   h->h32_e = e;
+  h->h32_R = R32;
   return pfe::ok();
 }
 
@@ -485,7 +557,8 @@ int64_t pfe_device_bytes(pfe_handle h) {
   const DevBuf* bufs[] = {&h->tile_ptr, &h->tile_vptr, &h->tile_cm, &h->tile_row, &h->tile_perm, &h->Ht,
                           &h->row_ptr, &h->col_idx, &h->H,    &h->transpose, &h->masses,
                           &h->H32,     &h->flags,   &h->wsA,  &h->wsB,       &h->wsC,
-                          &h->wsD,     &h->wsSmall, &h->wsRed, &h->wsOut,    &h->wsCk, &h->wsSlice};
+                          &h->wsD,     &h->wsSmall, &h->wsRed, &h->wsOut,    &h->wsCk, &h->wsSlice,
+                          &h->t32_ptr, &h->t32_vptr, &h->t32_cm, &h->t32_row, &h->t32_perm};
   int64_t s = 0;
   for (auto* b : bufs) s += (int64_t)b->bytes;
   return s;
@@ -585,6 +658,7 @@ static Err set_hessian_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const i
       h->tile_rows = 0;
       h->n_tiles = 0;
       h->tiled_R = 0;
+      h->release_tiles32();
       std::vector<int64_t> tp, tv, perm;
       std::vector<int32_t> tcm, trow, order;
       // Rows whose neighbours lie far away in the given numbering (an MD
@@ -641,6 +715,7 @@ static Err set_hessian_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const i
     h->tile_row.release();
     h->tile_perm.release();
     h->Ht.release();
+    h->release_tiles32();
   }
   PFE_TRY(sync(h));
   h->has_h = true;

@@ -337,3 +337,34 @@ def test_filter_rows_with_more_than_64_records(dense_cluster, tile_rows, monkeyp
         assert rel_err(dB, rG) < 1e-11
     finally:
         P.pfe_destroy(h)
+
+
+def test_fp32_tile_heights_on_one_handle(case, monkeypatch):
+    """The FP32 filter walks its own row tiles (three rows by default, the FP64
+    filter two); switching their height between calls on one handle rebuilds
+    the tiles and the FP32 block order, and every height gives the same bits
+    (each row sums its blocks in column order) and matches the oracle."""
+    banner("apply_filter fp32, tile heights 2/3/4 on one handle")
+    monkeypatch.delenv("PFEIG_TILE_ROWS", raising=False)
+    g = case.g
+    f = design(case, 25)
+    X = gaussian_block(case.n, 96, 51).astype(np.float32)
+    ref = chebyshev.apply_filter(case.H, f.c, f.e, f.coef, X.astype(np.float64))
+    h = P.pfe_create(0)
+    try:
+        P.pfe_set_hessian(h, g.row_ptr, g.col_idx, g.blocks, g.masses)
+        P.pfe_set_bounds(h, 0.0, case.ub)
+        out = []
+        for r32 in [None, "2", "4", "3", None]:
+            if r32 is None:
+                monkeypatch.delenv("PFEIG_TILE_ROWS_F32", raising=False)
+            else:
+                monkeypatch.setenv("PFEIG_TILE_ROWS_F32", r32)
+            out.append(P.pfe_apply_filter(h, f, X))
+        assert rel_err(out[0], ref) < 5e-5
+        for Y in out[1:]:
+            np.testing.assert_array_equal(Y, out[0])
+        Y64 = P.pfe_apply_filter(h, f, X.astype(np.float64))   # FP64 tiles untouched
+        assert rel_err(Y64, ref) < 1e-12
+    finally:
+        P.pfe_destroy(h)

@@ -254,11 +254,9 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
   // One branch-free block per set of streams, so every start value is
   // requested before the first wait (rows past the last read row 0 and are
   // never stored).
-  const char* rb[R];
+  int64_t rb[R];   // byte offset of each row's three matrix rows
 #pragma unroll
-  for (int r = 0; r < R; ++r)
-    rb[r] = reinterpret_cast<const char*>((int64_t)(rows[r] >= 0 ? rows[r] : 0) * ld3 *
-                                          (int64_t)sizeof(T));
+  for (int r = 0; r < R; ++r) rb[r] = (int64_t)(rows[r] >= 0 ? rows[r] : 0) * ld3 * (int64_t)sizeof(T);
   auto start2 = [&](const T* s1, T c1, const T* s2, T c2) {
     vt v1[R][3][NP], v2[R][3][NP];
 #pragma unroll
@@ -267,7 +265,7 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
       for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const int64_t o = reinterpret_cast<int64_t>(rb[r]) + boff[a][p];
+          const int64_t o = rb[r] + boff[a][p];
           v1[r][a][p] = ld_nt(reinterpret_cast<const vt*>(reinterpret_cast<const char*>(s1) + o));
           v2[r][a][p] = ld_nt(reinterpret_cast<const vt*>(reinterpret_cast<const char*>(s2) + o));
         }
@@ -286,7 +284,7 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
       for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const int64_t o = reinterpret_cast<int64_t>(rb[r]) + boff[a][p];
+          const int64_t o = rb[r] + boff[a][p];
           v1[r][a][p] = ld_nt(reinterpret_cast<const vt*>(reinterpret_cast<const char*>(s1) + o));
         }
 #pragma unroll

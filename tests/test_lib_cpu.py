@@ -127,3 +127,14 @@ def test_locality_order_rejects_bad_patterns():
         P.pfe_locality_order(np.array([0, 2, 1], dtype=np.int64), np.array([0, 1], dtype=np.int32))
     with pytest.raises(P.PfeError):
         P.pfe_locality_order(rp, np.array([0, 1, 1], dtype=np.int32), group=5)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for several it exits with status 2 and
+    says why, before touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""

@@ -414,8 +414,9 @@ Err cholqr2(pfe_handle h, const Small& sm, double* X, int64_t n, int q, int64_t 
     PFE_TRY(sync(h));
     if (pass == 0 && norm_bound > 0 && !(dmax <= norm_bound * norm_bound))
       return pfe::fail(PFE_EBOUNDS,
-                       "filtered vectors grew beyond the filter's bound on [-1, 1]: the "
-                       "spectrum exceeds [lam_lb, lam_ub]");
+                       "filtered vectors grew beyond the filter's bound on [-1, 1] (largest column "
+                       "norm " + std::to_string(std::sqrt(dmax)) + " > " + std::to_string(norm_bound) +
+                       "): the spectrum exceeds [lam_lb, lam_ub]");
     if (info != 0) {
       if (shifted_done || !(dmax > 0) || !std::isfinite(dmax))
         return pfe::fail(PFE_EBREAKDOWN, "CholQR breakdown (Gram matrix not positive definite)");
@@ -1111,8 +1112,12 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 4, fd.degree);
     }
     {
+      // Filtered columns obey the filter's bound; locked ones were carried
+      // over unfiltered with unit norm, so with any locked column the bound
+      // on the largest column norm is at least 1.
+      const double nbound = nf < q ? std::max(bound, 1.0 + 1e-9) : bound;
       Timer tm(h, &st.t_orth);
-      PFE_TRY(cholqr2(h, sm, Fout, n, q, ld, bound, &ga));
+      PFE_TRY(cholqr2(h, sm, Fout, n, q, ld, nbound, &ga));
     }
     if (Fout == W) {
       std::swap(h->wsA.p, h->wsB.p);
@@ -1560,7 +1565,10 @@ static Err sliced_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       todo.emplace_back(a, mid);
       continue;
     }
-    if (r) return r;
+    if (r)
+      return pfe::fail(r.st, "sub-window [" + std::to_string(a) + ", " + std::to_string(b) +
+                                 "] (margin " + std::to_string(os.eps) + ", degree " +
+                                 std::to_string(ss.degree) + "): " + r.msg);
     used.push_back(b);
     // merge the pairs near the cut a: old ones (end of `kept`) and new ones
     std::vector<int> order;          // final sequence of (negative: old slot, else new index)

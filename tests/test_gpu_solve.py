@@ -90,6 +90,31 @@ def test_solve_locking_same_pairs_fewer_columns(case, prec, tol):
         assert runs[1]["filter_columns"] <= 32 * runs[1]["iterations"]
 
 
+def test_solve_locking_with_a_filter_below_one(case):
+    """A narrow window with a wide margin gives a filter whose coefficients
+    sum to less than one (0.74 here), the bound on the filtered columns'
+    norms.  Locked columns are carried over unfiltered with norm 1, so the
+    growth check that guards the spectral bounds must allow them (it took
+    them for growth and returned EBOUNDS).  Eight exact in-window
+    eigenvectors lock after the first iteration, leaving 8 of 16 columns to
+    filter."""
+    banner("solve with locking, filter coefficients summing below one")
+    lam, i0 = case.lam, 1597
+    lo = 0.5 * (lam[i0 - 1] + lam[i0])
+    hi = 0.5 * (lam[i0 + 7] + lam[i0 + 8])
+    c, e = F.spectral_map(0.0, case.ub)
+    w = (hi - lo) / e
+    coef = F.filter_coefficients((lo - c) / e, (hi - c) / e, 0.5 * w, 400, F.NONE)
+    assert np.abs(coef).sum() < 0.8
+    X0 = gaussian_block(case.n, 16, 12)
+    X0[:, :8] = case.U[:, i0:i0 + 8]
+    out = P.pfe_solve_interval(case.h, lo, hi, 16, 16, degree=400, eps=0.5 * w, tol=1e-10,
+                               x0=X0, locking=1)
+    assert out["status"] == "PFE_OK", out["stats"]
+    np.testing.assert_allclose(out["evals"], lam[i0:i0 + 8], rtol=1e-10)
+    assert out["stats"]["filter_columns"] < 16 * out["stats"]["iterations"]
+
+
 def test_solve_fp32_form(case):
     banner("solve fp32-filter form N=1000")
     X0 = gaussian_block(case.n, 32, 11)

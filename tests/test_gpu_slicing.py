@@ -120,3 +120,24 @@ def test_sliced_degenerate_cluster_on_cut():
         check_window(H, lam, U, ub, lo, hi, out)
     finally:
         P.pfe_destroy(h)
+
+
+def test_sliced_fp32_form(case):
+    """The FP32-filter form under slicing: FP32 iterations, then FP64 sweeps
+    until tol, slice by slice."""
+    banner("sliced solve, FP32-filter form, 3 slices")
+    out = P.pfe_solve_sliced(case.h, case.lo, case.hi, 40, 32, n_slices=3, tol=1e-10,
+                             precision=P.PFE_FP32)
+    assert out["n_slices"] == 3
+    check_window(case.H, case.lam, case.U, case.ub, case.lo, case.hi, out)
+
+
+def test_sliced_dense_part_narrow_slices(case):
+    """33 eigenvalues high in the spectrum, 4 per slice: narrow sub-windows
+    whose adaptive margins are wide, so their filters' coefficients sum below
+    one while converged columns lock."""
+    banner("sliced solve, [13.7%, 14.5%] theta_max, 4 per slice")
+    lo, hi = 0.137 * case.th, 0.145 * case.th
+    out = P.pfe_solve_sliced(case.h, lo, hi, 64, 32, per_slice=4, tol=1e-10)
+    assert out["n_slices"] >= 6
+    check_window(case.H, case.lam, case.U, case.ub, lo, hi, out)

@@ -368,3 +368,25 @@ def test_fp32_tile_heights_on_one_handle(case, monkeypatch):
         assert rel_err(Y64, ref) < 1e-12
     finally:
         P.pfe_destroy(h)
+
+
+def test_new_pattern_on_a_handle_rebuilds_both_tile_sets(case):
+    """One handle, two patterns: the glass, then the same glass with its atoms
+    renumbered at random (same sizes; the scattered numbering takes the
+    locality order).  The second import must rebuild the FP64 and the FP32
+    row tiles; both filters match the oracle before and after."""
+    banner("apply_filter after a new pattern on the same handle (FP64 and FP32)")
+    f = design(case, 25)
+    X = gaussian_block(case.n, 96, 61)
+    g2 = relabel(case.g, 6)
+    H2 = hessian.glass_H(g2)[0]
+    h = P.pfe_create(0)
+    try:
+        for g, H in ((case.g, case.H), (g2, H2), (case.g, case.H)):
+            P.pfe_set_hessian(h, g.row_ptr, g.col_idx, g.blocks, g.masses)
+            P.pfe_set_bounds(h, 0.0, case.ub)
+            ref = chebyshev.apply_filter(H, f.c, f.e, f.coef, X)
+            assert rel_err(P.pfe_apply_filter(h, f, X.astype(np.float32)), ref) < 5e-5
+            assert rel_err(P.pfe_apply_filter(h, f, X), ref) < 1e-12
+    finally:
+        P.pfe_destroy(h)

@@ -1164,7 +1164,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     // fewer vectors than [xi - eps, eta + eps] has eigenvalues, Sec. 2.6):
     // raise the degree 1.5-fold, which shrinks eps by eq. thresh.
     // In the FP32 phase only a plateau above kFp32Floor counts: FP32 rounding
-    // floors lie below it (4e-7 at degree 400 on 1e5 atoms, 1.1e-5 at degree
+    // floors lie below it (2.1e-6 at degree 400 on 1e5 atoms, 1.1e-5 at degree
     // 1200 on 1e6), and a higher degree would only raise them.
     const bool plateau = it >= 3 && cnt == prev_cnt && mx > 0.7 * prev_max;
     stall = plateau ? stall + 1 : 0;

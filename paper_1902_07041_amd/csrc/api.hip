@@ -2022,17 +2022,30 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
   // (plus what its buffer already holds): no checkpoint copies and no
   // recomputation.  Segments keep length s for the block gradient, so the
   // results are bit-identical to the checkpointed sweep.
-  bool keep = false;
+  // The adjoint recurrence does not depend on the forward one (only the
+  // block gradient joins them) and both steps share alpha, beta and delta:
+  // when both trajectories fit, slot k of one buffer holds [t_k | a_{d-k+1}]
+  // side by side (2 ld columns) and one fused step advances both, the added
+  // stream being [0 | Ybar].  Same arithmetic per element, identical bits.
+  bool keep = false, pair = false;
   if (stride <= 0 && d >= 2) {
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess) keep = mv * (size_t)d <= fr / 2 + h->wsCk.bytes;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+      const size_t have = h->wsCk.bytes + h->wsC.bytes;
+      pair = nvec == ld && 2 * mv * (size_t)(d + 2) <= fr / 2 + have;
+      keep = pair || mv * (size_t)d <= fr / 2 + h->wsCk.bytes;
+    }
   }
-  // device: X, Ybar, a0/a1 pair, adjoint vectors of one segment, and either
-  // the trajectory or a segment buffer (s vectors) and checkpoints (2 per segment)
+  // device: X, Ybar and either the paired slots, or the adjoint vectors of
+  // one segment with the forward trajectory or with a segment buffer (s
+  // vectors) and checkpoints (2 per segment)
   PFE_HIP(h->wsA.ensure(mv * 2));                 // X, Ybar (device copies when host inputs)
-  PFE_HIP(h->wsB.ensure(mv * (size_t)(s + 2)));  // adjoint vectors of one segment
+  if (!pair) PFE_HIP(h->wsB.ensure(mv * (size_t)(s + 2)));   // adjoint vectors of one segment
   PFE_HIP(h->wsSmall.ensure((size_t)std::max(d, 1) * sizeof(double) + 64));
-  if (keep) {
+  if (pair) {
+    PFE_HIP(h->wsCk.ensure(2 * mv * (size_t)(d + 1)));   // slots 0 .. d
+    PFE_HIP(h->wsC.ensure(2 * mv));                       // [0 | Ybar]
+  } else if (keep) {
     PFE_HIP(h->wsCk.ensure(mv * (size_t)d));
   } else {
     PFE_HIP(h->wsC.ensure(mv * (size_t)std::max(s, 1)));
@@ -2059,6 +2072,52 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
     return pfe::cheb_step_f64(A, Hs, tin, prev, nullptr, out, nvec, ld, first ? a1 : a2,
                               first ? b1 : b2, first ? 0.0 : -1.0, 0.0, h->stream);
   };
+  if (pair) {
+    const int64_t ld2 = 2 * ld, nel2 = 2 * nel;
+    double* Z = h->wsCk.as<double>();      // slot k at Z + k nel2: [t_k | a_{d-k+1}]
+    double* Yc = h->wsC.as<double>();      // [0 | Ybar]
+    auto slot = [&](int k) { return Z + (size_t)k * nel2; };
+    PFE_HIP(pfe::zero_f64(Yc, nel2, h->stream));
+    PFE_HIP(pfe::copy_cols_f64(n, (int)ld, Yb, ld, Yc + ld, ld2, h->stream));
+    PFE_HIP(pfe::zero_f64(slot(0), nel2, h->stream));                     // a_{d+1} = 0
+    PFE_HIP(pfe::copy_cols_f64(n, (int)ld, Xd, ld, slot(0), ld2, h->stream));   // t_0 = X
+    // t_1 = H_hat X;  a_d = g_d Ybar (no matrix term)
+    PFE_HIP(pfe::cheb_step_f64(A, Hs, slot(0), nullptr, nullptr, slot(1), nvec, ld2, a1, b1, 0.0,
+                               0.0, h->stream));
+    PFE_HIP(pfe::cheb_step_f64(A, Hs, Yc + ld, nullptr, Yc + ld, slot(1) + ld, nvec, ld2, 0.0, 0.0,
+                               0.0, f->coef[d], h->stream));
+    // t_{s+1} = 2 H_hat t_s - t_{s-1} beside a_{d-s} = g_{d-s} Ybar + 2 H_hat a_{d-s+1} - a_{d-s+2}
+    for (int st = 1; st <= d - 1; ++st)
+      PFE_HIP(pfe::cheb_step_f64(A, Hs, slot(st), slot(st - 1), Yc, slot(st + 1), (int)ld2, ld2, a2,
+                                 b2, -1.0, f->coef[d - st], h->stream));
+    // a_0 = g_0 Ybar + H_hat a_1 - a_2, into the spent a_{d+1}
+    PFE_HIP(pfe::cheb_step_f64(A, Hs, slot(d) + ld, slot(d - 1) + ld, Yc + ld, slot(0) + ld, nvec,
+                               ld2, a1, b1, -1.0, f->coef[0], h->stream));
+    double* wdv = h->wsSmall.as<double>();
+    std::vector<double> wv((size_t)d, 2.0);
+    wv[0] = 1.0;
+    PFE_HIP(hipMemcpyAsync(wdv, wv.data(), d * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    // block gradient by segments, last first: t_k in slot k, a_{k+1} in slot d - k
+    for (int j = nseg - 1; j >= 0; --j) {
+      const int k0 = j * s, w1 = std::min(k0 + s, d) - k0;
+      PFE_HIP(pfe::sddmm_seg_f64(A, nvec, w1, slot(d - k0) + ld, -nel2, slot(k0), nel2, ld2,
+                                 wdv + k0, G, h->stream));
+    }
+    PFE_HIP(pfe::scale_f64(h->nnzb * 9, 1.0 / e, G, h->stream));
+    if (dev) {
+      PFE_HIP(pfe::copy_cols_f64(n, (int)ld, slot(0) + ld, ld2, dX, ld, h->stream));
+      PFE_HIP(hipMemcpyAsync(dblocks, G, h->nnzb * 9 * sizeof(double), hipMemcpyDeviceToDevice,
+                             h->stream));
+    } else {
+      double* a0 = h->wsA.as<double>();   // X's copy is spent
+      PFE_HIP(pfe::copy_cols_f64(n, (int)ld, slot(0) + ld, ld2, a0, ld, h->stream));
+      PFE_HIP(hipMemcpyAsync(dX, a0, mv, hipMemcpyDeviceToHost, h->stream));
+      PFE_HIP(hipMemcpyAsync(dblocks, G, h->nnzb * 9 * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+    }
+    PFE_TRY(sync(h));
+    return pfe::ok();
+  }
   double* traj = h->wsCk.as<double>();   // trajectory: t_k in slot k
   if (keep) {
     PFE_HIP(pfe::copy_cols_f64(n, (int)ld, Xd, ld, traj, ld, h->stream));

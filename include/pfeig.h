@@ -179,10 +179,12 @@ pfe_status pfe_apply_filter(pfe_handle h, const pfe_filter* f, int32_t nvec, con
  * over segments of ckpt_stride steps (0: ceil(sqrt(d))), each segment's block
  * gradient formed in one batched pass.  ckpt_stride > 0: the forward
  * recurrence vectors of a segment are recomputed from a checkpoint pair kept
- * per segment (2 ceil(d/s) + s vectors of workspace).  ckpt_stride = 0: all d
- * forward vectors are kept instead when they fit in half the free device
- * memory (no recomputation; the library holds that workspace until
- * pfe_destroy), checkpoints otherwise; both give identical results. */
+ * per segment (2 ceil(d/s) + s vectors of workspace).  ckpt_stride = 0: when
+ * the forward and the adjoint vectors fit in half the free device memory
+ * (2 (d + 2) vectors; nvec == ld), one fused step advances both recurrences
+ * side by side; else, when the d forward vectors fit, they are kept; else
+ * checkpoints.  No vector is recomputed in the first two cases; the library
+ * holds that workspace until pfe_destroy.  All give identical results. */
 pfe_status pfe_apply_filter_adjoint(pfe_handle h, const pfe_filter* f, int32_t nvec,
                                     const double* X, const double* dY, double* dX,
                                     double* dblocks, int64_t ld, int32_t ckpt_stride,

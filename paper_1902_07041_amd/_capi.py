@@ -330,8 +330,8 @@ def pfe_apply_filter(h, f: Filter, X, Y=None, precision=None):
 
 def pfe_apply_filter_adjoint(h, f: Filter, X, dY, nnzb: int, ckpt_stride: int = 0):
     """(dX, dblocks[nnzb,3,3]) of the FP64 filter.  ckpt_stride: steps per
-    segment; 0 lets the library choose ceil(sqrt(d)) and keep the whole
-    forward trajectory on the device when it fits (identical results)."""
+    segment; 0 lets the library choose ceil(sqrt(d)) and keep the forward
+    and adjoint vectors on the device when they fit (identical results)."""
     L = load_library()
     dX = _empty_like_side(X, tuple(X.shape), np.float64)
     dB = _empty_like_side(X, (nnzb, 3, 3), np.float64)

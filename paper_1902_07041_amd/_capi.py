@@ -328,10 +328,12 @@ def pfe_apply_filter(h, f: Filter, X, Y=None, precision=None):
     return Y
 
 
-def pfe_apply_filter_adjoint(h, f: Filter, X, dY, nnzb: int, ckpt_stride: int = 0):
+def pfe_apply_filter_adjoint(h, f: Filter, X, dY, nnzb: int, ckpt_stride: int = 0, nvec=None):
     """(dX, dblocks[nnzb,3,3]) of the FP64 filter.  ckpt_stride: steps per
     segment; 0 lets the library choose ceil(sqrt(d)) and keep the forward
-    and adjoint vectors on the device when they fit (identical results)."""
+    and adjoint vectors on the device when they fit (identical results).
+    nvec: the leading columns of X and dY that are vectors (default all; the
+    rest is row padding, and dX's padding columns are left undefined)."""
     L = load_library()
     dX = _empty_like_side(X, tuple(X.shape), np.float64)
     dB = _empty_like_side(X, (nnzb, 3, 3), np.float64)
@@ -341,8 +343,9 @@ def pfe_apply_filter_adjoint(h, f: Filter, X, dY, nnzb: int, ckpt_stride: int = 
     p_db, d4 = _arr(dB, np.float64, "dblocks")
     dev = _same_side(d1, d2, d3, d4)
     ld = int(X.shape[1])
+    nv = ld if nvec is None else int(nvec)
     cf = f.cstruct()
-    _check(h, L.pfe_apply_filter_adjoint(h, C.byref(cf), ld, p_x, p_dy, p_dx, p_db, ld,
+    _check(h, L.pfe_apply_filter_adjoint(h, C.byref(cf), nv, p_x, p_dy, p_dx, p_db, ld,
                                          ckpt_stride, PFE_DEVICE_PTRS if dev else 0))
     return dX, dB
 

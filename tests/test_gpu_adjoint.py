@@ -48,9 +48,11 @@ def test_adjoint_parity(tiny, d, stride, q):
 
 
 def test_adjoint_trajectory_equals_checkpoints(tiny):
-    """Stride 0 keeps the whole forward trajectory when it fits (it does at
-    this size); an explicit stride of the same ceil(sqrt d) recomputes each
-    segment from checkpoints.  Same segments, same kernels: identical bits."""
+    """Stride 0 keeps both trajectories and advances them side by side when
+    they fit (they do at this size), or the forward one alone when the rows
+    are padded; an explicit stride of the same ceil(sqrt d) recomputes each
+    segment from checkpoints.  Same segments, same per-element arithmetic:
+    identical bits in all three."""
     banner("adjoint, trajectory kept vs checkpoints, d=150")
     c, e = F.spectral_map(0.0, tiny.ub)
     xi, eta = (0.05 * tiny.lam[-1] - c) / e, (0.15 * tiny.lam[-1] - c) / e
@@ -63,6 +65,14 @@ def test_adjoint_trajectory_equals_checkpoints(tiny):
     dX1, dB1 = P.pfe_apply_filter_adjoint(tiny.h, f, X, W, tiny.g.nnzb, 13)
     np.testing.assert_array_equal(dX0, dX1)
     np.testing.assert_array_equal(dB0, dB1)
+    # rows padded to 24 columns: the recurrences cannot sit side by side in
+    # one step of 2 ld columns, so only the forward trajectory is kept
+    Xp = np.zeros((tiny.n, 24))
+    Wp = np.zeros((tiny.n, 24))
+    Xp[:, :16], Wp[:, :16] = X, W
+    dX2, dB2 = P.pfe_apply_filter_adjoint(tiny.h, f, Xp, Wp, tiny.g.nnzb, 0, nvec=16)
+    np.testing.assert_array_equal(dX2[:, :16], dX0)
+    np.testing.assert_array_equal(dB2, dB0)
 
 
 def test_hellmann_feynman_and_chain_rule(tiny):

@@ -172,6 +172,22 @@ pfe_status pfe_design_filter(double lam_lo, double lam_hi, double lam_lb, double
 pfe_status pfe_apply_filter(pfe_handle h, const pfe_filter* f, int32_t nvec, const void* X,
                             void* Y, int64_t ld, int32_t precision, uint32_t flags);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * filter of pfe_apply_filter, Y = pi(H_hat) X for nvec columns of device
+ * arrays X and Y ([n][ld], row-major, must not overlap), with the same
+ * kernels and the same results.  The recurrence's scratch multivector lives in
+ * a static device array of 256 MiB that each device holds from pfe_create
+ * until the process ends, so the call allocates nothing: n * ld * 8 must not
+ * exceed 268435456 bytes (EINVAL otherwise).  The call only enqueues work on
+ * the handle's stream and returns without synchronising; Y is complete when
+ * that work is.  Every call on one device shares the one scratch array: calls
+ * whose work overlaps in time on one device (other streams, other handles,
+ * other host threads) race and give wrong results.  EINVAL also for a bad
+ * filter, nvec or ld; ESTATE without a Hessian. */
+pfe_status pfe_apply_filter_noalloc(pfe_handle h, const pfe_filter* f, int32_t nvec,
+                                    const double* X, double* Y, int64_t ld);
+
 /* Reverse mode of pfe_apply_filter (FP64): given X and dY = dL/dY ([n][ld]),
  * returns dX = dL/dX ([n][ld]) and dblocks = dL/dH on every stored block
  * ([nnzb][3][3], each stored block an independent parameter, c and e held

@@ -113,6 +113,7 @@ def load_library():
     L.pfe_design_filter.argtypes = [dbl, dbl, dbl, dbl, C.POINTER(CFilterOpts), pd, i32,
                                     C.POINTER(CFilter)]
     L.pfe_apply_filter.argtypes = [vp, C.POINTER(CFilter), i32, vp, vp, i64, i32, u32]
+    L.pfe_apply_filter_noalloc.argtypes = [vp, C.POINTER(CFilter), i32, vp, vp, i64]
     L.pfe_apply_filter_adjoint.argtypes = [vp, C.POINTER(CFilter), i32, vp, vp, vp, vp, i64, i32,
                                            u32]
     L.pfe_eigvec_block_gradient.argtypes = [vp, i32, vp, vp, vp, u32]
@@ -133,7 +134,8 @@ def load_library():
     L.pfe_solve_lanczos.argtypes = [vp, dbl, dbl, i32, C.POINTER(CLanczosOpts), C.POINTER(i32), vp,
                                     vp, vp, C.POINTER(CSolveStats)]
     for name in ("pfe_create", "pfe_set_hessian", "pfe_set_springs", "pfe_estimate_bounds", "pfe_set_bounds",
-                 "pfe_design_filter", "pfe_apply_filter", "pfe_apply_filter_adjoint",
+                 "pfe_design_filter", "pfe_apply_filter", "pfe_apply_filter_noalloc",
+                 "pfe_apply_filter_adjoint",
                  "pfe_eigvec_block_gradient", "pfe_spring_gradient", "pfe_solve_interval",
                  "pfe_estimate_count", "pfe_solve_sliced", "pfe_count_moments", "pfe_design_dirac",
                  "pfe_solve_lanczos"):
@@ -325,6 +327,24 @@ def pfe_apply_filter(h, f: Filter, X, Y=None, precision=None):
     cf = f.cstruct()
     _check(h, L.pfe_apply_filter(h, C.byref(cf), ld, p_x, p_y, ld, precision,
                                  PFE_DEVICE_PTRS if dev else 0))
+    return Y
+
+
+def pfe_apply_filter_noalloc(h, f: Filter, X, Y, nvec=None):
+    """Y = p(H_hat) X (FP64) for device tensors X, Y [n][ld] with no device
+    allocation by the library.  Only enqueues the work on the handle's stream
+    (no synchronisation); nvec: leading columns to filter (default all)."""
+    L = load_library()
+    p_x, dx = _arr(X, np.float64, "X")
+    p_y, dy = _arr(Y, np.float64, "Y")
+    if not (dx and dy):
+        raise TypeError("pfe_apply_filter_noalloc takes device tensors only")
+    ld = int(X.shape[1])
+    if tuple(Y.shape) != tuple(X.shape):
+        raise TypeError("X and Y must have the same shape")
+    cf = f.cstruct()
+    _check(h, L.pfe_apply_filter_noalloc(h, C.byref(cf), ld if nvec is None else int(nvec), p_x, p_y,
+                                         ld))
     return Y
 
 

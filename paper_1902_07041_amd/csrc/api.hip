@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,40 @@
 
 using pfe::DevBuf;
 using pfe::Err;
+
+// Device scratch of pfe_apply_filter_noalloc: the second multivector of the
+// Clenshaw recurrence (the first is the caller's output), for callers that
+// cannot allocate.  Each device the library runs on holds its own copy until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: host code uses only the per-device address that
+// hipGetSymbolAddress returns (scratch_addr below).
+constexpr size_t kNoAllocScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxScratchDevices] = {};
+
+// Resolves the device address of `scratch` on `device`, which must be the
+// current device; once per device (later calls return the stored address).
+hipError_t init_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipSuccess;   // entry point refuses
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr[device] = p;
+  return hipSuccess;
+}
+
+void* scratch_addr(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_addr[device];
+}
+}  // namespace
 
 struct pfe_ctx {
   int device = 0;
@@ -228,7 +263,7 @@ struct Timer {
 // X is read only; the result lands in P, Q is scratch (P, Q, X distinct).
 // d launches for d >= 1.
 template <typename T>
-Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double a1, double b1,
+Err run_filter(pfe_handle h, const T* vals, const double* g, int d, double a1, double b1,
                const T* X, T* P, T* Q, int q, int64_t ld, int64_t* steps) {
   const pfe::Bsr A = sizeof(T) == 4 ? h->bsr32() : h->bsr();
   auto step = [&](const T* tin, const T* prev, T* out, double al, double be, double de,
@@ -241,7 +276,6 @@ Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double
                                 (const float*)X, (float*)out, q, ld, (float)al, (float)be,
                                 (float)de, (float)ze, h->stream);
   };
-  const int d = (int)g.size() - 1;
   if (d == 0) {
     PFE_HIP(step(X, nullptr, P, 0.0, 0.0, 0.0, g[0]));
     if (steps) *steps += 1;
@@ -273,6 +307,12 @@ Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double
   }
   if (steps) *steps += d;
   return pfe::ok();
+}
+
+template <typename T>
+Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double a1, double b1,
+               const T* X, T* P, T* Q, int q, int64_t ld, int64_t* steps) {
+  return run_filter<T>(h, vals, g.data(), (int)g.size() - 1, a1, b1, X, P, Q, q, ld, steps);
 }
 
 // FP32 row tiles of height R32 over the FP64 tiles' pattern and order.
@@ -521,6 +561,8 @@ pfe_status pfe_create(int device, void* hip_stream, pfe_handle* out) {
   h->device = device;
   if ((e = hipSetDevice(device)) != hipSuccess)
     return create_fail(h, PFE_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  if ((e = init_scratch(device)) != hipSuccess)
+    return create_fail(h, PFE_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
   if (hip_stream) {
     h->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -974,6 +1016,35 @@ pfe_status pfe_apply_filter(pfe_handle h, const pfe_filter* f, int32_t nvec, con
                             void* Y, int64_t ld, int32_t precision, uint32_t flags) {
   if (!h) return PFE_EINVAL;
   return finish(h, apply_impl(h, f, nvec, X, Y, ld, precision, flags));
+}
+
+// The FP64 filter of apply_impl on device arrays with the recurrence's
+// scratch multivector in `scratch`: no allocation, no synchronisation.
+static Err apply_noalloc_impl(pfe_handle h, const pfe_filter* f, int nvec, const double* X,
+                              double* Y, int64_t ld) {
+  PFE_TRY(select_device(h));
+  PFE_TRY(check_filter(h, f));
+  if (nvec < 1 || ld < nvec || !X || !Y) return pfe::fail(PFE_EINVAL, "need 1 <= nvec <= ld and arrays");
+  double* Q = static_cast<double*>(scratch_addr(h->device));
+  if (!Q) return pfe::fail(PFE_ESTATE, "no scratch address for this device");
+  const int64_t n = h->n();
+  const double bytes = (double)n * (double)ld * sizeof(double);
+  if (bytes > (double)kNoAllocScratchBytes)
+    return pfe::fail(PFE_EINVAL, "n * ld * 8 = " + std::to_string((long long)bytes) +
+                                     " bytes exceeds the allocation-free scratch of " +
+                                     std::to_string((long long)kNoAllocScratchBytes) + " bytes");
+  const uintptr_t x0 = reinterpret_cast<uintptr_t>(X), y0 = reinterpret_cast<uintptr_t>(Y);
+  const uintptr_t span = (uintptr_t)bytes;
+  if (x0 < y0 + span && y0 < x0 + span) return pfe::fail(PFE_EINVAL, "X and Y overlap");
+  PFE_TRY(run_filter<double>(h, h->step_vals64(), f->coef, f->degree, 1.0 / f->e, -f->c / f->e, X,
+                             Y, Q, nvec, ld, nullptr));
+  return pfe::ok();
+}
+
+pfe_status pfe_apply_filter_noalloc(pfe_handle h, const pfe_filter* f, int32_t nvec,
+                                    const double* X, double* Y, int64_t ld) {
+  if (!h) return PFE_EINVAL;
+  return finish(h, apply_noalloc_impl(h, f, nvec, X, Y, ld));
 }
 
 // ------------------------------------------------------------------ solve

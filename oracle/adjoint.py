@@ -78,6 +78,49 @@ def filter_vjp_blocks(H, row_ptr, col_idx, c, e, coef, X, Ybar):
     return a[0], G / e
 
 
+def filter_vjp_block_sample(Hhat, e, coef, X, Ybar, row_ptr, col_idx, blocks):
+    """(Xbar, G[blocks]): the sums of filter_vjp_blocks for the listed stored
+    blocks only, for sizes where every t_k and a_k cannot be kept: both
+    recurrences run in full, but of each vector only the rows of the atoms
+    the listed blocks touch are kept.  Hhat(V) returns H_hat V."""
+    blocks = np.asarray(blocks, dtype=np.int64)
+    bi = block_rows(row_ptr)[blocks]
+    bj = np.asarray(col_idx, dtype=np.int64)[blocks]
+    atoms = np.unique(np.concatenate([bi, bj]))
+    where = {int(a): s for s, a in enumerate(atoms)}
+    rows = (3 * atoms[:, None] + np.arange(3)[None, :]).ravel()
+    coef = np.asarray(coef, dtype=np.float64)
+    d = coef.shape[0] - 1
+    # forward: t_0 .. t_{d-1} at the kept rows
+    tk = []
+    t_prev = np.array(X, dtype=np.float64)
+    tk.append(t_prev[rows])
+    if d >= 2:
+        t_cur = Hhat(t_prev)
+        tk.append(t_cur[rows])
+        for _ in range(2, d):
+            t_prev, t_cur = t_cur, 2.0 * Hhat(t_cur) - t_prev
+            tk.append(t_cur[rows])
+    # reverse: a_d .. a_1 at the kept rows, then a_0
+    ak = [None] * (d + 2)
+    a_next2 = np.zeros_like(Ybar)          # a_{k+2}
+    a_next = np.zeros_like(Ybar)           # a_{k+1}
+    for k in range(d, 0, -1):
+        a_k = coef[k] * Ybar + 2.0 * Hhat(a_next) - a_next2
+        ak[k] = a_k[rows]
+        a_next2, a_next = a_next, a_k
+    Xbar = coef[0] * Ybar + (Hhat(a_next) if d >= 1 else 0.0) - a_next2
+    G = np.zeros((blocks.shape[0], 3, 3))
+    for s in range(blocks.shape[0]):
+        ri = slice(3 * where[int(bi[s])], 3 * where[int(bi[s])] + 3)
+        rj = slice(3 * where[int(bj[s])], 3 * where[int(bj[s])] + 3)
+        if d >= 1:
+            G[s] += ak[1][ri] @ tk[0][rj].T
+        for k in range(1, d):
+            G[s] += 2.0 * (ak[k + 1][ri] @ tk[k][rj].T)
+    return Xbar, G / e
+
+
 def spring_chain_rule(G, hblocks, row_ptr, col_idx, pairs, unit, masses):
     """(dL/dk [P], dL/dm [N]) from block gradients G (untied blocks)."""
     rows = block_rows(row_ptr)
@@ -101,6 +144,61 @@ def spring_chain_rule(G, hblocks, row_ptr, col_idx, pairs, unit, masses):
     np.add.at(dm, cols, inner)
     dm *= -0.5 / masses
     return dk, dm
+
+
+def spring_loss_central_difference(Hhat, e, coef, X, W, i, j, u, m_i, m_j, h):
+    """Central difference [L(k + h) - L(k - h)] / (2 h) of L(k) = <W, p(H_hat) X>
+    in the spring constant k of the spring between atoms i and j (unit vector
+    u), with c and e held constant; Hhat(V) returns H_hat V = (H V - c V) / e.
+
+    H depends on k through H_ii += k u u^T / m_i, H_jj += k u u^T / m_j,
+    H_ij = H_ji -= k u u^T / sqrt(m_i m_j) (eq. intro.2 with K_ij = -k u u^T),
+    so H_hat(k +- h) = H_hat +- h E_hat with E_hat = dH/dk / e, which is zero
+    outside the rows and columns of atoms i and j.  Subtracting two FP64 losses
+    would lose the quotient to cancellation at large n (their rounding, about
+    1e-14 |L|, divided by 2h = 2e-6), so the quotient is formed from the two
+    recurrences of Algorithm 2 directly: with T+-_k their vectors,
+    S_k = (T+_k + T-_k) / 2 and D_k = (T+_k - T-_k) / (2 h) obey
+        S_0 = X, D_0 = 0, S_1 = H_hat X, D_1 = E_hat X,
+        S_{k+1} = 2 H_hat S_k - S_{k-1} + 2 h^2 E_hat D_k,
+        D_{k+1} = 2 H_hat D_k - D_{k-1} + 2 E_hat S_k,
+    and the quotient is sum_k g_k <W, D_k>, equal to the two-evaluation
+    difference in exact arithmetic.  S and D are advanced side by side as
+    one block [S | D]."""
+    uu = np.outer(u, u)
+    si, sj = slice(3 * i, 3 * i + 3), slice(3 * j, 3 * j + 3)
+    mij = np.sqrt(m_i * m_j)
+
+    def Ehat_rows(V):
+        """Rows of atoms i and j of E_hat V (its only nonzero rows)."""
+        return ((uu @ V[si] / m_i - uu @ V[sj] / mij) / e,
+                (uu @ V[sj] / m_j - uu @ V[si] / mij) / e)
+
+    coef = np.asarray(coef, dtype=np.float64)
+    d = coef.shape[0] - 1
+    if d == 0:
+        return 0.0
+    q = X.shape[1]
+    prev = np.hstack([X, np.zeros_like(X)]).astype(np.float64)      # [S_0 | D_0]
+    cur = Hhat(np.hstack([X, np.zeros_like(X)]))                     # [S_1 | D_1]
+    cur[:, q:] = 0.0
+    ei, ej = Ehat_rows(X)
+    cur[si, q:] += ei
+    cur[sj, q:] += ej
+    quot = coef[1] * float(np.einsum("rc,rc->", W, cur[:, q:]))
+    for k in range(1, d):
+        es_i, es_j = Ehat_rows(cur[:, :q])          # E_hat S_k
+        ed_i, ed_j = Ehat_rows(cur[:, q:])          # E_hat D_k
+        nxt = Hhat(cur)
+        nxt *= 2.0
+        nxt -= prev
+        nxt[si, :q] += 2.0 * h * h * ed_i
+        nxt[sj, :q] += 2.0 * h * h * ed_j
+        nxt[si, q:] += 2.0 * es_i
+        nxt[sj, q:] += 2.0 * es_j
+        prev, cur = cur, nxt
+        quot += coef[k + 1] * float(np.einsum("rc,rc->", W, cur[:, q:]))
+    return quot
 
 
 def hellmann_feynman_blocks(v, row_ptr, col_idx):

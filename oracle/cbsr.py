@@ -49,6 +49,8 @@ class BsrOperator:
 
     def __matmul__(self, X):
         X = np.asarray(X, dtype=np.float64)
+        if X.shape[0] != self.shape[1]:
+            raise ValueError(f"operand has {X.shape[0]} rows, the operator {self.shape[1]} columns")
         vec = X.ndim == 1
         Xc = np.ascontiguousarray(X.reshape(X.shape[0], -1))
         Y = np.empty_like(Xc)

@@ -49,6 +49,16 @@ def spring_blocks(row_ptr, col_idx, pairs, unit, k) -> np.ndarray:
     return K
 
 
+def mapped_blocks(row_ptr, col_idx, hblocks, c: float, e: float) -> np.ndarray:
+    """Blocks of H_hat = (H - c I) / e (eq. transf.1): c subtracted on the
+    diagonal of every diagonal block, every block divided by e."""
+    rows = block_rows(row_ptr)
+    out = np.array(hblocks, dtype=np.float64, copy=True)
+    diag = rows == np.asarray(col_idx, dtype=np.int64)
+    out[diag] -= c * np.eye(3)
+    return out / e
+
+
 def to_bsr(row_ptr, col_idx, hblocks) -> sp.bsr_matrix:
     n_atoms = row_ptr.shape[0] - 1
     return sp.bsr_matrix((np.ascontiguousarray(hblocks), np.asarray(col_idx, dtype=np.int64),

@@ -15,8 +15,8 @@ step on H itself.  Readings of the paper taken here:
 * Residual rho_i = ||H x_i - theta_i x_i|| / lambda_ub, with lambda_ub the
   same upper bound of ||H|| = lambda_max that defines the spectral map.
 * Stop when every Ritz value within delta of the window has rho_i <= tol in
-  two consecutive iterations with an unchanged in-window count, and at least
-  three iterations have run (a window can look empty after one or two).
+  two consecutive iterations with an unchanged in-window count (so at the
+  earliest after the second iteration).
 """
 from __future__ import annotations
 

@@ -117,6 +117,57 @@ def test_spring_chain_rule_vs_finite_differences(tiny):
         assert dm[i] == pytest.approx((L_of(g.k, mp) - L_of(g.k, mm)) / 2e-4, rel=1e-6, abs=1e-10)
 
 
+def test_spring_central_difference_recurrence(tiny):
+    """The cancellation-free central difference of the filter loss in one
+    spring constant equals the plain two-evaluation quotient: to rounding at
+    a large step (where the plain quotient loses nothing to cancellation,
+    and the h^2 term matters), to the plain quotient's own rounding at
+    h = 1e-6, and to the chain-rule derivative of the adjoint to O(h^2)."""
+    g, H, hb, Hd, lam, U, c, e, coef, X, W = tiny
+    from synth.glass import assemble_blocks
+    Xbar, G = adjoint.filter_vjp_blocks(H, g.row_ptr, g.col_idx, c, e, coef, X, W)
+    dk, _ = adjoint.spring_chain_rule(G, hb, g.row_ptr, g.col_idx, g.pairs, g.unit, g.masses)
+
+    def L_of(k):
+        rp, ci, kb = assemble_blocks(g.n_atoms, g.pairs, g.unit, k)
+        return loss(hessian.to_bsr(rp, ci, hessian.weight_blocks(rp, ci, kb, g.masses)), c, e, coef, X, W)
+    rng = np.random.default_rng(31)
+    for p in rng.choice(g.k.shape[0], 6, replace=False):
+        i, j = int(g.pairs[p, 0]), int(g.pairs[p, 1])
+        args = (chebyshev.mapped_matvec(H, c, e), e, coef, X, W, i, j, g.unit[p], g.masses[i],
+                g.masses[j])
+        # the plain quotient at h = 1e-6 carries its own rounding, about
+        # 1e-15 |L| / h = 5e-9 here
+        for hstep, rel, ab in [(0.3, 1e-11, 0.0), (1e-6, 1e-6, 1e-9 * abs(dk).max())]:
+            kp = g.k.copy(); kp[p] += hstep
+            km = g.k.copy(); km[p] -= hstep
+            plain = (L_of(kp) - L_of(km)) / (2 * hstep)
+            quot = adjoint.spring_loss_central_difference(*args, hstep)
+            assert quot == pytest.approx(plain, rel=rel, abs=ab)
+        assert adjoint.spring_loss_central_difference(*args, 1e-6) == pytest.approx(dk[p], rel=1e-9)
+
+
+def test_block_sample_vjp_equals_full_vjp(tiny):
+    """The memory-lean block-sample VJP reproduces the full one on the
+    sampled blocks and in Xbar (same sums, other bookkeeping)."""
+    g, H, hb, Hd, lam, U, c, e, coef, X, W = tiny
+    Xbar, G = adjoint.filter_vjp_blocks(H, g.row_ptr, g.col_idx, c, e, coef, X, W)
+    pick = np.random.default_rng(3).choice(hb.shape[0], 25, replace=False)
+    for co in (coef, coef[:2], coef[:1]):
+        Xb, Gs = adjoint.filter_vjp_block_sample(chebyshev.mapped_matvec(H, c, e), e, co, X, W,
+                                                 g.row_ptr, g.col_idx, pick)
+        Xr, Gr = adjoint.filter_vjp_blocks(H, g.row_ptr, g.col_idx, c, e, co, X, W)
+        np.testing.assert_allclose(Xb, Xr, rtol=0, atol=1e-13 * np.abs(Xr).max())
+        np.testing.assert_allclose(Gs, Gr[pick], rtol=0, atol=1e-13 * max(np.abs(Gr).max(), 1e-300))
+
+
+def test_mapped_blocks(tiny):
+    """H_hat's blocks (eq. transf.1) against (H - c I) / e formed densely."""
+    g, H, hb, Hd, lam, U, c, e, coef, X, W = tiny
+    Hh = hessian.to_dense(g.row_ptr, g.col_idx, hessian.mapped_blocks(g.row_ptr, g.col_idx, hb, c, e))
+    np.testing.assert_allclose(Hh, (Hd - c * np.eye(Hd.shape[0])) / e, rtol=0, atol=1e-15)
+
+
 def test_hellmann_feynman(tiny):
     g, H, hb, Hd, lam, U, c, e, coef, X, W = tiny
     from synth.glass import assemble_blocks

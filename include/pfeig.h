@@ -191,16 +191,20 @@ pfe_status pfe_apply_filter_noalloc(pfe_handle h, const pfe_filter* f, int32_t n
 /* Reverse mode of pfe_apply_filter (FP64): given X and dY = dL/dY ([n][ld]),
  * returns dX = dL/dX ([n][ld]) and dblocks = dL/dH on every stored block
  * ([nnzb][3][3], each stored block an independent parameter, c and e held
- * constant), by the adjoint recurrence a_k = g_k dY + 2 H_hat a_{k+1} - a_{k+2},
- * over segments of ckpt_stride steps (0: ceil(sqrt(d))), each segment's block
- * gradient formed in one batched pass.  ckpt_stride > 0: the forward
- * recurrence vectors of a segment are recomputed from a checkpoint pair kept
- * per segment (2 ceil(d/s) + s vectors of workspace).  ckpt_stride = 0: when
- * the forward and the adjoint vectors fit in half the free device memory
- * (2 (d + 2) vectors; nvec == ld), one fused step advances both recurrences
- * side by side; else, when the d forward vectors fit, they are kept; else
- * checkpoints.  No vector is recomputed in the first two cases; the library
- * holds that workspace until pfe_destroy.  All give identical results. */
+ * constant), by the adjoint recurrence a_k = g_k dY + 2 H_hat a_{k+1} - a_{k+2}
+ * (the reverse of Algorithm 2's recurrence), over segments of s = ckpt_stride
+ * steps (0: ceil(sqrt(d))), each segment's block gradient formed in one
+ * batched pass.  The forward recurrence vectors of a segment are recomputed
+ * from a checkpoint pair kept per segment (2 ceil(d/s) + 2 s + 2 vectors of
+ * workspace, about one more forward filter of work).  flags may add
+ * PFE_ADJOINT_RESIDENT (with ckpt_stride = 0): when the forward and the
+ * adjoint vectors fit in half the free device memory (2 (d + 2) vectors;
+ * nvec == ld), one fused step advances both recurrences side by side; else,
+ * when the d forward vectors fit, they are kept; else checkpoints as above
+ * (also when that workspace cannot be allocated).  No vector is recomputed in
+ * the resident cases, and the library holds their workspace until
+ * pfe_destroy.  All modes give identical results. */
+#define PFE_ADJOINT_RESIDENT 4u
 pfe_status pfe_apply_filter_adjoint(pfe_handle h, const pfe_filter* f, int32_t nvec,
                                     const double* X, const double* dY, double* dX,
                                     double* dblocks, int64_t ld, int32_t ckpt_stride,
@@ -237,8 +241,19 @@ typedef struct {
   int32_t precision;   /* PFE_FP64, or PFE_FP32: FP32 filter with FP64
                           orthonormalisation, Rayleigh-Ritz and residuals until
                           the residuals plateau at the FP32 rounding floor (or
-                          come within 30 tol), then FP64 refinement sweeps until
-                          converged: one when that floor is within reach of tol */
+                          come within 30 tol), then one FP64 refinement sweep:
+                          m FP64 filter applications, each followed by CholQR2,
+                          then Rayleigh-Ritz and the residual check.  m (at most
+                          16) is the number of applications that takes the
+                          residual below tol at the contraction rate kappa,
+                          the larger of min_j |pi(theta_j)| / min_i
+                          |pi(theta_i)| (j over the Ritz values, i over those
+                          near the window) and the FP32 iterations' last
+                          contraction before the plateau, from min(plateau,
+                          kappa x the previous iteration's largest
+                          near-window residual).  If
+                          the residuals still exceed tol: ENOCONV with the
+                          converged pairs (see refine_sweeps) */
   uint64_t seed;       /* start block seed when x0 == NULL */
   const double* x0;    /* optional start block [n][block] (host, or device with
                           PFE_DEVICE_PTRS in flags) */
@@ -251,6 +266,9 @@ typedef struct {
                           the Rayleigh-Ritz step, so they keep improving and
                           rejoin the filtered set if their residual grows.
                           0: every column is filtered in every iteration. */
+  int32_t refine_sweeps; /* FP32 form: refinement sweeps allowed (0 -> 1, the
+                          method's one sweep); more than one is opt-in, each
+                          further sweep sized from the residual the last left */
 } pfe_solve_opts;
 
 typedef struct {
@@ -272,6 +290,9 @@ typedef struct {
   int32_t n_window;          /* in-window Ritz values at the end */
   int64_t filter_columns;    /* sum over iterations of the filtered columns */
   double t_gemm;             /* seconds in those MFMA kernels (events on the stream) */
+  int32_t shifted_passes;    /* CholQR breakdowns answered by a shifted pass (or, for a
+                                rank-deficient start block, by a refilled column) */
+  int32_t refine_applications; /* FP64 filter applications in the refinement sweeps */
 } pfe_solve_stats;
 
 /* Fill opts with defaults (block 0 must then be set by the caller). */
@@ -286,8 +307,8 @@ void pfe_solve_opts_default(pfe_solve_opts* opts);
  * PFE_DEVICE_PTRS in opts->flags; may be NULL), resid[nev] =
  * ||H v - lambda v|| / lam_ub (host, may be NULL), stats (may be NULL).
  * Stops when every Ritz value within 1e-6 lam_ub of the window has a
- * residual <= tol in two consecutive iterations with the same in-window
- * count (and at least three iterations have run).  ECAPACITY: *n_found = number of in-window Ritz values, which
+ * residual <= tol in the current iteration, the in-window count equals the
+ * previous iteration's, and at least three iterations have run.  ECAPACITY: *n_found = number of in-window Ritz values, which
  * exceeds nev, or equals the block (every Ritz value in the window, so the
  * block cannot show the count is complete); nothing else written.  ENOCONV: the converged in-window pairs are
  * returned. */
@@ -357,7 +378,10 @@ pfe_status pfe_solve_lanczos(pfe_handle h, double lam_lo, double lam_hi, int32_t
  * (explicit cuts, or where the count estimate of eq. eigval_count_estimator
  * from pfe_count_moments reaches equal shares), each solved like
  * pfe_solve_interval with opts (block, r, smoothing, tol, max_iter, precision,
- * locking, seed; degree, eps and x0 are ignored) and a filter margin of
+ * locking, seed, refine_sweeps; degree, eps and x0 are ignored; with
+ * refine_sweeps 0 the FP32 form's sub-solves may run up to 8 refinement
+ * sweeps, since a sub-window that falls short is split and splitting does not
+ * help the refinement) and a filter margin of
  * `margin` times its width (degree by eq. thresh).  Interior cuts are widened
  * by 1e-8 lam_ub on both sides; pairs within that guard are grouped by
  * eigenvalue (a gap above 1e-9 lam_ub starts a new group) and each group is

@@ -11,6 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 PFE_DEVICE_PTRS = 1
 PFE_BLOCKS_ARE_H = 2
+PFE_ADJOINT_RESIDENT = 4
 PFE_SMOOTH_NONE, PFE_SMOOTH_JACKSON, PFE_SMOOTH_LANCZOS = 0, 1, 2
 PFE_FP64, PFE_FP32 = 0, 1
 STATUS = {0: "PFE_OK", -1: "PFE_EINVAL", -2: "PFE_ENOTSYM", -3: "PFE_ENOMEM", -4: "PFE_EHIP",
@@ -40,7 +41,8 @@ class CSolveOpts(C.Structure):
     _fields_ = [("block", C.c_int32), ("degree", C.c_int32), ("eps", C.c_double),
                 ("r", C.c_double), ("smoothing", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
-                ("x0", C.c_void_p), ("flags", C.c_uint32), ("locking", C.c_int32)]
+                ("x0", C.c_void_p), ("flags", C.c_uint32), ("locking", C.c_int32),
+                ("refine_sweeps", C.c_int32)]
 
 
 class CDiracFilter(C.Structure):
@@ -68,7 +70,8 @@ class CSolveStats(C.Structure):
                 ("filter_bytes", C.c_double), ("t_total", C.c_double), ("t_filter", C.c_double),
                 ("t_orth", C.c_double), ("t_rr", C.c_double), ("t_resid", C.c_double),
                 ("gemm_flops", C.c_double), ("max_resid", C.c_double), ("n_window", C.c_int32),
-                ("filter_columns", C.c_int64), ("t_gemm", C.c_double)]
+                ("filter_columns", C.c_int64), ("t_gemm", C.c_double),
+                ("shifted_passes", C.c_int32), ("refine_applications", C.c_int32)]
 
 
 _lib = None
@@ -348,10 +351,12 @@ def pfe_apply_filter_noalloc(h, f: Filter, X, Y, nvec=None):
     return Y
 
 
-def pfe_apply_filter_adjoint(h, f: Filter, X, dY, nnzb: int, ckpt_stride: int = 0, nvec=None):
+def pfe_apply_filter_adjoint(h, f: Filter, X, dY, nnzb: int, ckpt_stride: int = 0, nvec=None,
+                             resident: bool = False):
     """(dX, dblocks[nnzb,3,3]) of the FP64 filter.  ckpt_stride: steps per
-    segment; 0 lets the library choose ceil(sqrt(d)) and keep the forward
-    and adjoint vectors on the device when they fit (identical results).
+    checkpoint segment (0: ceil(sqrt(d))).  resident (with ckpt_stride 0):
+    PFE_ADJOINT_RESIDENT, keep the forward (and adjoint) vectors on the
+    device when they fit instead of recomputing them (identical results).
     nvec: the leading columns of X and dY that are vectors (default all; the
     rest is row padding, and dX's padding columns are left undefined)."""
     L = load_library()
@@ -366,7 +371,8 @@ def pfe_apply_filter_adjoint(h, f: Filter, X, dY, nnzb: int, ckpt_stride: int = 
     nv = ld if nvec is None else int(nvec)
     cf = f.cstruct()
     _check(h, L.pfe_apply_filter_adjoint(h, C.byref(cf), nv, p_x, p_dy, p_dx, p_db, ld,
-                                         ckpt_stride, PFE_DEVICE_PTRS if dev else 0))
+                                         ckpt_stride, (PFE_DEVICE_PTRS if dev else 0) |
+                                         (PFE_ADJOINT_RESIDENT if resident else 0)))
     return dX, dB
 
 
@@ -402,7 +408,7 @@ def pfe_spring_gradient(h, pairs, unit, dblocks, n_atoms: int):
 def pfe_solve_interval(h, lam_lo, lam_hi, nev, block, degree=0, eps=0.0, r=0.0,
                        smoothing=PFE_SMOOTH_NONE, tol=0.0, max_iter=100, precision=PFE_FP64,
                        seed=11, x0=None, want_vectors=True, vectors_on_device=False,
-                       allow_noconv=False, locking=1):
+                       allow_noconv=False, locking=1, refine_sweeps=0):
     """Eigenpairs in [lam_lo, lam_hi].  Returns a dict with evals, evecs
     ([n_found][n], numpy or a GPU tensor), resid, stats, status."""
     L = load_library()
@@ -411,6 +417,7 @@ def pfe_solve_interval(h, lam_lo, lam_hi, nev, block, degree=0, eps=0.0, r=0.0,
     o.block, o.degree, o.eps, o.r, o.smoothing = block, degree, eps, r, smoothing
     o.tol, o.max_iter, o.precision, o.seed = tol, max_iter, precision, seed
     o.locking = locking
+    o.refine_sweeps = refine_sweeps
     p_x0, dx = _arr(x0, np.float64, "x0")
     o.x0 = p_x0
     o.flags = PFE_DEVICE_PTRS if (dx or vectors_on_device) else 0
@@ -445,7 +452,7 @@ def pfe_solve_interval(h, lam_lo, lam_hi, nev, block, degree=0, eps=0.0, r=0.0,
 def pfe_solve_sliced(h, lam_lo, lam_hi, nev, block, n_slices=0, per_slice=0, margin=0.0,
                      count_degree=0, count_samples=0, count_seed=13, cuts=None, r=0.0,
                      smoothing=PFE_SMOOTH_NONE, tol=0.0, max_iter=100, precision=PFE_FP64, seed=11,
-                     locking=1, want_vectors=True, vectors_on_device=False):
+                     locking=1, want_vectors=True, vectors_on_device=False, refine_sweeps=0):
     """Eigenpairs in [lam_lo, lam_hi] by spectrum slicing.  Returns a dict with
     evals, evecs ([n_found][n]), resid, stats, status, n_slices and the
     sub-window boundaries."""
@@ -454,6 +461,7 @@ def pfe_solve_sliced(h, lam_lo, lam_hi, nev, block, n_slices=0, per_slice=0, mar
     L.pfe_solve_opts_default(C.byref(o))
     o.block, o.r, o.smoothing, o.tol, o.max_iter = block, r, smoothing, tol, max_iter
     o.precision, o.seed, o.locking = precision, seed, locking
+    o.refine_sweeps = refine_sweeps
     o.flags = PFE_DEVICE_PTRS if vectors_on_device else 0
     so = CSliceOpts()
     so.n_slices, so.per_slice, so.margin = n_slices, per_slice, margin

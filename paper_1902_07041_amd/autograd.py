@@ -4,8 +4,10 @@
                        backward: chain rule through H_ij = K_ij / sqrt(m_i m_j)
                        with K_ij = -k u u^T (pfe_spring_gradient)
     ChebFilter         (X, H blocks) -> p_d(H_hat) X  (Algorithm 2's operator)
-                       backward: adjoint recurrence with sqrt(d) checkpoints
-                       (pfe_apply_filter_adjoint), giving dX and dL/dH per block
+                       backward: adjoint recurrence over checkpoint segments of
+                       ceil(sqrt(d)) steps, recomputing each segment's forward
+                       vectors (pfe_apply_filter_adjoint; `resident` keeps them
+                       on the device instead), giving dX and dL/dH per block
     WindowEigenvalues  H blocks -> eigenvalues of H in [lo, hi] (and their
                        eigenvectors, not differentiable)
                        backward: Hellmann-Feynman, dL/dH = sum_s (dL/dlam_s) v_s v_s^T
@@ -79,9 +81,12 @@ class SpringSystem:
         """H blocks of the network with spring constants k [P] and masses [N]."""
         return AssembleSprings.apply(k, masses, self)
 
-    def filter(self, X, hblocks, f: C.Filter, ckpt_stride: int = 0):
-        """p_d(H_hat) X for the filter f, X [n, q] on this GPU."""
-        return ChebFilter.apply(X, hblocks, self, f, ckpt_stride)
+    def filter(self, X, hblocks, f: C.Filter, ckpt_stride: int = 0, resident: bool = False):
+        """p_d(H_hat) X for the filter f, X [n, q] on this GPU.  The backward
+        pass recomputes the forward vectors from checkpoints every ckpt_stride
+        steps (0: ceil(sqrt(d))); resident=True keeps them instead when they
+        fit in device memory (same results)."""
+        return ChebFilter.apply(X, hblocks, self, f, ckpt_stride, resident)
 
     def window_eigenvalues(self, hblocks, lam_lo, lam_hi, nev, block, bounds, **solve_kw):
         """(eigenvalues [m], eigenvectors [m, n]) of H in [lam_lo, lam_hi]; bounds
@@ -116,11 +121,12 @@ class AssembleSprings(torch.autograd.Function):
 
 class ChebFilter(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, X, hblocks, sysm: SpringSystem, f: C.Filter, ckpt_stride: int):
+    def forward(ctx, X, hblocks, sysm: SpringSystem, f: C.Filter, ckpt_stride: int,
+                resident: bool = False):
         sysm._load(hblocks, sysm._held[2] if sysm._held else None)
         X = X.detach().contiguous()
         Y = C.pfe_apply_filter(sysm.h, f, X)
-        ctx.sysm, ctx.f, ctx.stride = sysm, f, ckpt_stride
+        ctx.sysm, ctx.f, ctx.stride, ctx.resident = sysm, f, ckpt_stride, resident
         ctx.save_for_backward(X, hblocks)
         return Y
 
@@ -129,9 +135,10 @@ class ChebFilter(torch.autograd.Function):
         sysm = ctx.sysm
         X, hblocks = ctx.saved_tensors
         sysm._load(hblocks, sysm._held[2] if sysm._held else None)
-        dX, dH = C.pfe_apply_filter_adjoint(sysm.h, ctx.f, X, dY.contiguous(), sysm.nnzb, ctx.stride)
+        dX, dH = C.pfe_apply_filter_adjoint(sysm.h, ctx.f, X, dY.contiguous(), sysm.nnzb, ctx.stride,
+                                            resident=ctx.resident)
         return (dX if ctx.needs_input_grad[0] else None,
-                dH if ctx.needs_input_grad[1] else None, None, None, None)
+                dH if ctx.needs_input_grad[1] else None, None, None, None, None)
 
 
 class WindowEigenvalues(torch.autograd.Function):

@@ -218,6 +218,11 @@ constexpr double kOrderFarMax = 0.05;
 // for their rounding floor (and answered by FP64 refinement, not by a higher
 // degree).
 constexpr double kFp32Floor = 1e-3;
+// Most FP64 filter applications in one refinement sweep of the FP32 form.
+constexpr int kMaxRefineApps = 16;
+// Refinement sweeps a sub-window of a sliced FP32-form solve may run when the
+// caller leaves refine_sweeps at 0.
+constexpr int kSliceRefineSweeps = 8;
 
 // Algorithmic HBM bytes of one filter application of degree d >= 1 by the
 // Clenshaw recurrence (d launches): every launch reads the matrix values,
@@ -426,20 +431,30 @@ Err ensure_red(pfe_handle h, int64_t n, int q) {
 // CholQR2 of X [n][ld] (q columns) in place.  If a factorisation breaks
 // down, one shifted pass (shift 11 (n q + q (q + 1)) u tr(G) bound, the
 // shifted CholeskyQR of Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa)
-// is inserted and followed by the two plain passes.  On the first pass the
-// largest squared column norm is compared with `norm_bound`^2 (EBOUNDS).
-// Time and flops of the MFMA kernels (Gram and tall GEMM), 2 n q^2 each.
+// is inserted and followed by the two plain passes.  That recovers blocks
+// with a condition number up to about 1/u.  A block of lower rank (a start
+// block with repeated columns, say) breaks down again after the shift: then
+// with `refill` the column at the failed pivot, which the preceding columns
+// span, is replaced by a seeded Gaussian one and the factorisation starts
+// over (at most q times), as Householder QR would complete the basis
+// (without, EBREAKDOWN: a caller that needs the block to stay orthogonal to
+// other vectors refills and projects on its own).  On the first
+// pass the largest squared column norm is compared with `norm_bound`^2
+// (EBOUNDS).  Time and flops of the MFMA kernels (Gram and tall GEMM),
+// 2 n q^2 each; `shifted` counts shifted passes and refilled columns.
 struct GemmAcct {
   double t = 0, flops = 0;
   bool on = false;
 };
 
 Err cholqr2(pfe_handle h, const Small& sm, double* X, int64_t n, int q, int64_t ld,
-            double norm_bound, GemmAcct* ga = nullptr) {
+            double norm_bound, GemmAcct* ga = nullptr, int* shifted = nullptr,
+            bool refill = false) {
   const bool tg = ga && ga->on;
   const double f2 = 2.0 * (double)n * q * q;
   int passes = 2;
   bool shifted_done = false;
+  int refills = 0;
   for (int pass = 0; pass < passes; ++pass) {
     {
       Timer tm(h, tg ? &ga->t : nullptr, 1);
@@ -458,8 +473,21 @@ Err cholqr2(pfe_handle h, const Small& sm, double* X, int64_t n, int q, int64_t 
                        "norm " + std::to_string(std::sqrt(dmax)) + " > " + std::to_string(norm_bound) +
                        "): the spectrum exceeds [lam_lb, lam_ub]");
     if (info != 0) {
-      if (shifted_done || !(dmax > 0) || !std::isfinite(dmax))
+      if (!(dmax > 0) || !std::isfinite(dmax))
         return pfe::fail(PFE_EBREAKDOWN, "CholQR breakdown (Gram matrix not positive definite)");
+      if (shifted_done) {
+        // rank deficient: refill the dependent column and start over
+        if (!refill || refills >= q || info < 1 || info > q)
+          return pfe::fail(PFE_EBREAKDOWN, "CholQR breakdown (rank-deficient block)");
+        PFE_HIP(pfe::gaussian_fill_f64(n, 1, X + (info - 1), ld, 0x5EED0000ull + refills, h->stream));
+        ++refills;
+        if (shifted) ++*shifted;
+        shifted_done = false;
+        passes = 2;
+        pass = -1;
+        norm_bound = -1.0;
+        continue;
+      }
       const double u = std::ldexp(1.0, -53);
       const double shift = 11.0 * ((double)n * q + (double)q * (q + 1)) * u * (dmax * q);
       PFE_HIP(pfe::chol_inv_f64(q, sm.G, shift, sm.Rinv, sm.info, nullptr, h->stream));
@@ -468,6 +496,7 @@ Err cholqr2(pfe_handle h, const Small& sm, double* X, int64_t n, int q, int64_t 
       if (info != 0)
         return pfe::fail(PFE_EBREAKDOWN, "shifted CholQR breakdown");
       shifted_done = true;
+      if (shifted) ++*shifted;
       passes += 1;
     }
     {
@@ -1115,7 +1144,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   const int max_degree = std::min(200000, 8 * std::max(fd.degree, 1));
   {
     Timer tm(h, &st.t_orth);
-    PFE_TRY(cholqr2(h, sm, X, n, q, ld, -1.0));
+    PFE_TRY(cholqr2(h, sm, X, n, q, ld, -1.0, nullptr, &st.shifted_passes, true));
   }
   const double delta = 1e-6 * h->lam_ub;
   std::vector<double> theta, res;
@@ -1127,6 +1156,10 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   std::vector<int> perm(q);
   GemmAcct ga;
   ga.on = true;
+  const int max_sweeps = o.refine_sweeps > 0 ? o.refine_sweeps : 1;
+  int refine_m = 1;         // filter applications of the current refinement sweep
+  double refine_kap = 0.0;  // contraction per application it was sized for
+  double prev2_max = HUGE_VAL;
   for (int it = 1; it <= o.max_iter; ++it) {
     // Locking: the Ritz vectors of the last Rayleigh-Ritz step that lie in the
     // window with residual <= tol are not filtered.  The others (rounded up
@@ -1166,10 +1199,26 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     }
     st.filter_columns += nf;
     if (fp64_phase) {
-      Timer tm(h, &st.t_filter);
-      PFE_TRY(run_filter<double>(h, h->step_vals64(), fd.coef, 1.0 / fd.e, -fd.c / fd.e, Fin, Fout,
-                                 (double*)R, nf, ld, &st.filter_steps));
-      st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 8, fd.degree);
+      // A refinement sweep of the FP32 form applies the filter refine_m
+      // times, orthonormalising between applications (Algorithm 4's QR after
+      // every filter step, its Rayleigh-Ritz step only after the last);
+      // otherwise once.
+      const int reps = (mixed && st.refined) ? refine_m : 1;
+      for (int rep = 0; rep < reps; ++rep) {
+        if (rep > 0) {
+          {
+            Timer tm(h, &st.t_orth);
+            PFE_TRY(cholqr2(h, sm, Fout, n, q, ld, bound, &ga, &st.shifted_passes));
+          }
+          std::swap(Fin, Fout);
+          st.filter_columns += nf;
+        }
+        Timer tm(h, &st.t_filter);
+        PFE_TRY(run_filter<double>(h, h->step_vals64(), fd.coef, 1.0 / fd.e, -fd.c / fd.e, Fin,
+                                   Fout, (double*)R, nf, ld, &st.filter_steps));
+        st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 8, fd.degree);
+        if (mixed) st.refine_applications++;
+      }
       st.fp64_iterations++;
     } else {
       float* X32 = (float*)R;
@@ -1188,7 +1237,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       // on the largest column norm is at least 1.
       const double nbound = nf < q ? std::max(bound, 1.0 + 1e-9) : bound;
       Timer tm(h, &st.t_orth);
-      PFE_TRY(cholqr2(h, sm, Fout, n, q, ld, nbound, &ga));
+      PFE_TRY(cholqr2(h, sm, Fout, n, q, ld, nbound, &ga, &st.shifted_passes));
     }
     if (Fout == W) {
       std::swap(h->wsA.p, h->wsB.p);
@@ -1208,19 +1257,56 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       }
       if (theta[j] >= lam_lo && theta[j] <= lam_hi) ++cnt;
     }
+    // Contraction of the slowest wanted Ritz vector per filter application:
+    // its error along an eigenvector outside the subspace shrinks by
+    // |pi(lambda)| / |pi(theta_i)| per application, and every eigenvalue
+    // outside the subspace has |pi| at most the smallest |pi| of the q Ritz
+    // values (the subspace holds the q largest), so min_j |pi(theta_j)| over
+    // the smallest near-window |pi(theta_i)| bounds the rate.
+    auto rate_bound = [&]() {
+      double pall = HUGE_VAL, pwin = HUGE_VAL;
+      for (int j = 0; j < q; ++j) {
+        const double x = std::min(1.0, std::max(-1.0, (theta[j] - fd.c) / fd.e));
+        const double v = std::fabs(pfe::cheb_value(fd.coef, x));
+        pall = std::min(pall, v);
+        if (theta[j] >= lam_lo - delta && theta[j] <= lam_hi + delta) pwin = std::min(pwin, v);
+      }
+      if (!(pwin > 0) || !std::isfinite(pwin)) return 0.0;
+      return std::min(pall / pwin, 1.0);
+    };
+    // Filter applications a refinement sweep needs to take the largest
+    // near-window residual from rho to tol at rate kap (at most
+    // kMaxRefineApps).
+    auto sweep_apps = [&](double rho, double kap) {
+      kap = std::min(kap, 0.95);
+      if (!(rho > o.tol) || !(kap > 0)) return 1;
+      const double m = std::ceil(std::log(o.tol / rho) / std::log(kap));
+      return (int)std::min<double>(kMaxRefineApps, std::max(1.0, m));
+    };
     if (trace)
-      std::fprintf(stderr, "[pfeig] it %d %s in-window %d max-resid(near) %.3e t=%.3fs\n", it,
-                   fp64_phase ? "fp64" : "fp32", cnt, mx,
+      std::fprintf(stderr, "[pfeig] it %d %s in-window %d max-resid(near) %.3e rate-bound %.3e t=%.3fs\n",
+                   it, fp64_phase ? "fp64" : "fp32", cnt, mx, rate_bound(),
                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
-    if (fp64_phase && st.refined) {
-      // FP64 refinement sweeps from the FP32 subspace: one when the FP32
-      // plateau was within reach of tol, more when its filter separates the
-      // window slowly (each sweep gains what one FP64 iteration gains)
+    if (fp64_phase && mixed) {
+      // after the FP64 refinement sweep: done, or ENOCONV with the converged
+      // pairs, unless the caller allows further sweeps
       if (ok_all) {
         converged = true;
         break;
       }
+      if (st.refined >= max_sweeps) break;
       ++st.refined;
+      // the sweep just run measured the rate (its first application also
+      // removed the FP32 rounding, so the measured rate can be too low)
+      const double measured = std::pow(mx / prev_max, 1.0 / refine_m);
+      refine_kap = std::max({refine_kap, rate_bound(), measured});
+      refine_m = sweep_apps(mx, refine_kap);
+      if (trace) std::fprintf(stderr, "[pfeig] refinement sweep %d: %d FP64 filter applications\n",
+                              st.refined, refine_m);
+      prev_cnt = cnt;
+      prev2_max = prev_max;
+      prev_max = mx;
+      continue;
     }
     // Stop as Algorithm 4 does once the wanted pairs have converged: every
     // Ritz value near the window meets tol, and the in-window count is the
@@ -1252,11 +1338,24 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     if (!fp64_phase && it >= 2 && cnt == prev_cnt &&
         ((mx > 0.5 * prev_max && mx <= kFp32Floor) || mx <= 30.0 * o.tol)) {
       // FP32 iterations have stalled at their rounding level (or are within
-      // reach of tol): FP64 refinement from here
+      // reach of tol): the FP64 refinement sweep from here.  Its rate is the
+      // larger of the Ritz values' bound and the last contraction the FP32
+      // iterations showed before the plateau (the bound can come out low
+      // when the block holds many more vectors than the window, whose Ritz
+      // values are poor).  The plateau is FP32 rounding spread over every
+      // eigendirection, most of which the first FP64 application removes;
+      // what decays at the slow rate is at most the previous iteration's
+      // residual times that rate.
       fp64_phase = true;
       st.refined = 1;
+      const double seen = (prev2_max > 0 && std::isfinite(prev2_max)) ? prev_max / prev2_max : 0.0;
+      refine_kap = std::max(rate_bound(), seen);
+      refine_m = sweep_apps(std::min(mx, refine_kap * prev_max), refine_kap);
+      if (trace) std::fprintf(stderr, "[pfeig] refinement sweep 1: %d FP64 filter applications\n",
+                              refine_m);
     }
     prev_cnt = cnt;
+    prev2_max = prev_max;
     prev_max = mx;
   }
   st.gemm_flops = ga.flops;
@@ -1586,6 +1685,10 @@ static Err sliced_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       }
     }
     os.x0 = nullptr;
+    // a sub-window of the FP32 form whose one refinement sweep falls short
+    // would be split, which narrows it without helping the refinement: the
+    // sub-solves may run further sweeps unless the caller set a number
+    if (os.refine_sweeps <= 0) os.refine_sweeps = kSliceRefineSweeps;
     os.seed = o.seed + 7919ull * (uint64_t)slice_no;
     os.flags = PFE_DEVICE_PTRS;
     const int base = (int)kept.size();
@@ -1601,6 +1704,8 @@ static Err sliced_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     agg.iterations += ss.iterations;
     agg.fp64_iterations += ss.fp64_iterations;
     agg.refined += ss.refined;
+    agg.refine_applications += ss.refine_applications;
+    agg.shifted_passes += ss.shifted_passes;
     agg.degree = std::max(agg.degree, ss.degree);
     agg.filter_steps += ss.filter_steps;
     agg.filter_bytes += ss.filter_bytes;
@@ -2088,22 +2193,25 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
   const int nseg = d > 0 ? (d + s - 1) / s : 0;
   const size_t mv = (size_t)n * ld * sizeof(double);
   const int64_t nel = n * ld;
-  // With the stride left to the library, the whole forward trajectory (t_k
-  // for k < d) stays on the device when it fits in half the free memory
-  // (plus what its buffer already holds): no checkpoint copies and no
-  // recomputation.  Segments keep length s for the block gradient, so the
-  // results are bit-identical to the checkpointed sweep.
-  // The adjoint recurrence does not depend on the forward one (only the
-  // block gradient joins them) and both steps share alpha, beta and delta:
-  // when both trajectories fit, slot k of one buffer holds [t_k | a_{d-k+1}]
+  // Default: the sweep keeps a checkpoint pair (t_k, t_{k+1}) at the start
+  // of every segment of s steps and regenerates the segment's forward
+  // vectors from it on the way back (2 ceil(d/s) + 2 s + 2 vectors).
+  // PFE_ADJOINT_RESIDENT (stride left to the library): the whole forward
+  // trajectory (t_k for k < d) stays on the device instead when it fits in
+  // half the free memory: no checkpoint copies and no recomputation.  The
+  // adjoint recurrence does not depend on the forward one (only the block
+  // gradient joins them) and both steps share alpha, beta and delta: when
+  // both trajectories fit, slot k of one buffer holds [t_k | a_{d-k+1}]
   // side by side (2 ld columns) and one fused step advances both, the added
-  // stream being [0 | Ybar].  Same arithmetic per element, identical bits.
+  // stream being [0 | Ybar].  Segments keep length s for the block gradient
+  // and every element sees the same arithmetic, so all three give identical
+  // bits.  A resident workspace that cannot be allocated falls back to
+  // checkpoints.
   bool keep = false, pair = false;
-  if (stride <= 0 && d >= 2) {
+  if ((flags & PFE_ADJOINT_RESIDENT) && stride <= 0 && d >= 2) {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
-      const size_t have = h->wsCk.bytes + h->wsC.bytes;
-      pair = nvec == ld && 2 * mv * (size_t)(d + 2) <= fr / 2 + have;
+      pair = nvec == ld && 2 * mv * (size_t)(d + 2) <= fr / 2 + h->wsCk.bytes;
       keep = pair || mv * (size_t)d <= fr / 2 + h->wsCk.bytes;
     }
   }
@@ -2111,14 +2219,24 @@ static Err adjoint_impl(pfe_handle h, const pfe_filter* f, int nvec, const doubl
   // one segment with the forward trajectory or with a segment buffer (s
   // vectors) and checkpoints (2 per segment)
   PFE_HIP(h->wsA.ensure(mv * 2));                 // X, Ybar (device copies when host inputs)
-  if (!pair) PFE_HIP(h->wsB.ensure(mv * (size_t)(s + 2)));   // adjoint vectors of one segment
   PFE_HIP(h->wsSmall.ensure((size_t)std::max(d, 1) * sizeof(double) + 64));
   if (pair) {
-    PFE_HIP(h->wsCk.ensure(2 * mv * (size_t)(d + 1)));   // slots 0 .. d
-    PFE_HIP(h->wsC.ensure(2 * mv));                       // [0 | Ybar]
-  } else if (keep) {
-    PFE_HIP(h->wsCk.ensure(mv * (size_t)d));
-  } else {
+    if (h->wsCk.ensure(2 * mv * (size_t)(d + 1)) != hipSuccess ||   // slots 0 .. d
+        h->wsC.ensure(2 * mv) != hipSuccess) {                      // [0 | Ybar]
+      (void)hipGetLastError();   // clear the failed allocation's error
+      h->wsCk.release();
+      pair = false;
+    }
+  }
+  if (!pair && keep) {
+    if (h->wsCk.ensure(mv * (size_t)d) != hipSuccess) {
+      (void)hipGetLastError();
+      h->wsCk.release();
+      keep = false;
+    }
+  }
+  if (!pair) PFE_HIP(h->wsB.ensure(mv * (size_t)(s + 2)));   // adjoint vectors of one segment
+  if (!pair && !keep) {
     PFE_HIP(h->wsC.ensure(mv * (size_t)std::max(s, 1)));
     PFE_HIP(h->wsCk.ensure(mv * (size_t)std::max(2 * nseg, 1)));
   }

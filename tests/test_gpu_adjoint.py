@@ -23,22 +23,29 @@ def tiny():
     P.pfe_destroy(c.h)
 
 
-@pytest.mark.parametrize("d,stride,q", [(12, 0, 3), (12, 5, 3), (1, 0, 2), (0, 0, 2), (31, 4, 64),
-                                        (7, 1, 70), (60, 10, 64), (150, 0, 16), (200, 0, 8)])
-def test_adjoint_parity(tiny, d, stride, q):
+@pytest.mark.parametrize("d,stride,q,resident",
+                         [(12, 0, 3, False), (12, 5, 3, False), (1, 0, 2, False), (0, 0, 2, False),
+                          (31, 4, 64, False), (7, 1, 70, False), (60, 10, 64, False),
+                          (150, 0, 16, False), (200, 0, 8, False), (150, 0, 16, True),
+                          (60, 0, 70, True), (60, 0, 96, True), (60, 0, 96, False)])
+def test_adjoint_parity(tiny, d, stride, q, resident):
     """Segments of the checkpointed reverse sweep hold `stride` steps
-    (ceil(sqrt d) by default): up to 5 here with the first five cases, 10
-    and 13 (d = 150, the benchmark's degree) and 15 (d = 200) with the last
-    three, so every register-resident segment kernel (8, 13 and 16 steps)
-    and the q > 64 path are compared with the oracle."""
-    banner(f"adjoint d={d} stride={stride} q={q}")
+    (ceil(sqrt d) by default): up to 5 here with the first five cases, 8, 10
+    and 13 (d = 150, the benchmark's degree) and 15 (d = 200) with the later
+    ones, so every register-resident segment kernel (8, 13 and 16 steps)
+    and the q > 64 path are compared with the oracle.  The resident cases
+    keep both trajectories and advance them side by side (they fit at this
+    size): at q = 70 and 96 that fused step runs over 2 ld = 144 and 192
+    columns, in two column passes, and the block gradient reads the adjoint
+    vectors with a negative stride."""
+    banner(f"adjoint d={d} stride={stride} q={q} resident={resident}")
     c, e = F.spectral_map(0.0, tiny.ub)
     xi, eta = (0.05 * tiny.lam[-1] - c) / e, (0.15 * tiny.lam[-1] - c) / e
     coef = F.filter_coefficients(xi, eta, 0.05, d, F.NONE)
     f = P.Filter(d, 0, c, e, xi, eta, 0.05, coef)
     X = gaussian_block(tiny.n, q, 21)
     W = gaussian_block(tiny.n, q, 22)
-    dX, dB = P.pfe_apply_filter_adjoint(tiny.h, f, X, W, tiny.g.nnzb, stride)
+    dX, dB = P.pfe_apply_filter_adjoint(tiny.h, f, X, W, tiny.g.nnzb, stride, resident=resident)
     rX, rG = adjoint.filter_vjp_blocks(tiny.H, tiny.g.row_ptr, tiny.g.col_idx, c, e, coef, X, W)
     assert rel_err(dX, rX) < 1e-12
     if d >= 1:
@@ -48,11 +55,11 @@ def test_adjoint_parity(tiny, d, stride, q):
 
 
 def test_adjoint_trajectory_equals_checkpoints(tiny):
-    """Stride 0 keeps both trajectories and advances them side by side when
-    they fit (they do at this size), or the forward one alone when the rows
-    are padded; an explicit stride of the same ceil(sqrt d) recomputes each
-    segment from checkpoints.  Same segments, same per-element arithmetic:
-    identical bits in all three."""
+    """The resident mode keeps both trajectories and advances them side by
+    side when they fit (they do at this size), or the forward one alone when
+    the rows are padded; the default (stride 0, ceil(sqrt d) = 13) and an
+    explicit stride of 13 recompute each segment from checkpoints.  Same
+    segments, same per-element arithmetic: identical bits in all four."""
     banner("adjoint, trajectory kept vs checkpoints, d=150")
     c, e = F.spectral_map(0.0, tiny.ub)
     xi, eta = (0.05 * tiny.lam[-1] - c) / e, (0.15 * tiny.lam[-1] - c) / e
@@ -61,16 +68,20 @@ def test_adjoint_trajectory_equals_checkpoints(tiny):
     f = P.Filter(d, 0, c, e, xi, eta, 0.05, coef)
     X = gaussian_block(tiny.n, 16, 23)
     W = gaussian_block(tiny.n, 16, 24)
-    dX0, dB0 = P.pfe_apply_filter_adjoint(tiny.h, f, X, W, tiny.g.nnzb, 0)
+    dX0, dB0 = P.pfe_apply_filter_adjoint(tiny.h, f, X, W, tiny.g.nnzb, 0, resident=True)
     dX1, dB1 = P.pfe_apply_filter_adjoint(tiny.h, f, X, W, tiny.g.nnzb, 13)
+    dX3, dB3 = P.pfe_apply_filter_adjoint(tiny.h, f, X, W, tiny.g.nnzb, 0)
     np.testing.assert_array_equal(dX0, dX1)
     np.testing.assert_array_equal(dB0, dB1)
+    np.testing.assert_array_equal(dX3, dX1)
+    np.testing.assert_array_equal(dB3, dB1)
     # rows padded to 24 columns: the recurrences cannot sit side by side in
     # one step of 2 ld columns, so only the forward trajectory is kept
     Xp = np.zeros((tiny.n, 24))
     Wp = np.zeros((tiny.n, 24))
     Xp[:, :16], Wp[:, :16] = X, W
-    dX2, dB2 = P.pfe_apply_filter_adjoint(tiny.h, f, Xp, Wp, tiny.g.nnzb, 0, nvec=16)
+    dX2, dB2 = P.pfe_apply_filter_adjoint(tiny.h, f, Xp, Wp, tiny.g.nnzb, 0, nvec=16,
+                                          resident=True)
     np.testing.assert_array_equal(dX2[:, :16], dX0)
     np.testing.assert_array_equal(dB2, dB0)
 

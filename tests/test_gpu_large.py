@@ -1,7 +1,6 @@
 """GPU parity at the two larger configurations, where no reference spectrum is
 affordable on the CPU: properties that hold at any size, each recomputed on
-the CPU with the oracle.  Both are opt-in (PFE_LARGE_TESTS=1): each holds the
-GPU for minutes, longer than a default test run should.
+the CPU with the oracle.
 
 * N = 1e6 (n = 3e6): the FP32-filter form (FP32 block values, vectors and
   accumulation; CholQR2 and Rayleigh-Ritz in FP64; one FP64 refinement
@@ -10,16 +9,15 @@ GPU for minutes, longer than a default test run should.
   (golden/glass1m_window.json, written by golden/make_large_windows.py).
   That window is 0.028 % of theta_max wide; at the configured degree 250 the
   filter margins reach far beyond the block's 160 columns, so the solve runs
-  at degree 1200.  Checked: the same number of eigenpairs, eigenvalues
-  within the sum of their residual bounds of each other, residuals
-  ||H v - lambda v|| / lambda_ub
-  recomputed with the oracle's BSR product, orthonormality, and the count
-  against the estimate (a coarse check: few probes, and a damped kernel that
-  blurs the window's ends).
+  at degree 1200.  Checked: the same number of eigenpairs, eigenvalues of the
+  two forms within 1e-8 relative of each other, exactly one refinement sweep,
+  residuals ||H v - lambda v|| / lambda_ub recomputed with the oracle's BSR
+  product, orthonormality, and the count against the estimate (a coarse
+  check: few probes, and a damped kernel that blurs the window's ends).
 * N = 4e6 (n = 1.2e7), the largest single-GPU instance: Lanczos bounds
   against the oracle, one filter application at block 256 (FP64 and FP32)
   against the oracle on sampled columns, the time per filter step and the
-  device memory footprint.  A full solve there takes longer than a test may.
+  device memory footprint.
 """
 import json
 import os
@@ -34,9 +32,7 @@ from synth import gaussian_block, gaussian_vector, lattice_glass
 
 from gpu_common import banner, rel_err
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(os.environ.get("PFE_LARGE_TESTS") != "1",
-                                 reason="minutes per case; set PFE_LARGE_TESTS=1")]
+pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(__file__)
 
@@ -53,47 +49,73 @@ def check_pairs(H, out, ub, tol, label):
     assert np.abs(G - np.eye(lam.size)).max() <= 1e-9
 
 
-def test_config_1m_mixed_precision_vs_fp64(monkeypatch):
-    monkeypatch.setenv("PFEIG_TRACE", "1")               # one line per outer iteration
+class Case1m:
+    pass
+
+
+@pytest.fixture(scope="module")
+def glass1m():
     gd = json.load(open(os.path.join(HERE, "golden", "glass1m_window.json")))
-    block, degree = 160, 1200
     banner(f"glass N={gd['n_atoms']} (drawing)")
-    g = lattice_glass(gd["n_atoms"], seed=gd["seed"])
-    hb = hessian.weight_blocks(g.row_ptr, g.col_idx, g.blocks, g.masses)
-    H = cbsr.BsrOperator(g.row_ptr, g.col_idx, hb)
-    h = P.pfe_create(0)
-    try:
-        P.pfe_set_hessian(h, g.row_ptr, g.col_idx, g.blocks, g.masses)
-        lb, ub, th = P.pfe_estimate_bounds(h, gd["lanczos_steps"], gaussian_vector(g.n, gd["v0_seed"]))
-        assert abs(th - gd["theta_max"]) <= 1e-10 * th
-        lo, hi = gd["lo_frac"] * th, gd["hi_frac"] * th
-        X0 = gaussian_block(g.n, block, 11)
-        banner(f"FP64 solve, block {block}, degree {degree}")
-        t0 = time.perf_counter()
-        r64 = P.pfe_solve_interval(h, lo, hi, block, block, degree=degree, tol=1e-10, x0=X0)
-        t64 = time.perf_counter() - t0
-        banner(f"FP64 solve {t64:.1f} s; FP32-filter solve")
-        t0 = time.perf_counter()
-        r32 = P.pfe_solve_interval(h, lo, hi, block, block, degree=degree, tol=1e-8, x0=X0,
-                                   precision=P.PFE_FP32)
-        t32 = time.perf_counter() - t0
-        mem = P.pfe_device_bytes(h)
-    finally:
-        P.pfe_destroy(h)
-    n64, n32 = r64["evals"].size, r32["evals"].size
-    banner(f"found {n64} (FP64, {t64:.1f} s) and {n32} (FP32 form, {t32:.1f} s); estimate "
-           f"{gd['count_estimate']:.1f} +- {gd['count_stderr']:.1f}; library device memory "
+    s = Case1m()
+    s.gd = gd
+    s.g = lattice_glass(gd["n_atoms"], seed=gd["seed"])
+    hb = hessian.weight_blocks(s.g.row_ptr, s.g.col_idx, s.g.blocks, s.g.masses)
+    s.H = cbsr.BsrOperator(s.g.row_ptr, s.g.col_idx, hb)
+    s.h = P.pfe_create(0)
+    P.pfe_set_hessian(s.h, s.g.row_ptr, s.g.col_idx, s.g.blocks, s.g.masses)
+    s.lb, s.ub, s.th = P.pfe_estimate_bounds(s.h, gd["lanczos_steps"],
+                                             gaussian_vector(s.g.n, gd["v0_seed"]))
+    s.lo, s.hi = gd["lo_frac"] * s.th, gd["hi_frac"] * s.th
+    s.block, s.degree = 160, 1200
+    s.X0 = gaussian_block(s.g.n, s.block, 11)
+    s.out = {}
+    yield s
+    P.pfe_destroy(s.h)
+
+
+def test_config_1m_fp64(glass1m, monkeypatch):
+    monkeypatch.setenv("PFEIG_TRACE", "1")               # one line per outer iteration
+    s = glass1m
+    assert abs(s.th - s.gd["theta_max"]) <= 1e-10 * s.th
+    banner(f"N=1e6 FP64 solve, block {s.block}, degree {s.degree}")
+    t0 = time.perf_counter()
+    r64 = P.pfe_solve_interval(s.h, s.lo, s.hi, s.block, s.block, degree=s.degree, tol=1e-10,
+                               x0=s.X0)
+    r64["time"] = time.perf_counter() - t0
+    s.out["fp64"] = r64
+    banner(f"FP64 solve {r64['time']:.1f} s, {r64['evals'].size} pairs, "
+           f"{r64['stats']['iterations']} iterations")
+    assert r64["status"] == "PFE_OK"
+    gd = s.gd
+    assert abs(r64["evals"].size - gd["count_estimate"]) <= 4 * gd["count_stderr"] + 0.25 * gd["count_estimate"]
+    check_pairs(s.H, r64, s.ub, 1e-10, "FP64")
+
+
+def test_config_1m_mixed_precision_one_sweep(glass1m, monkeypatch):
+    monkeypatch.setenv("PFEIG_TRACE", "1")
+    s = glass1m
+    if "fp64" not in s.out:
+        pytest.skip("needs the FP64 solve")
+    r64 = s.out["fp64"]
+    banner(f"N=1e6 FP32-filter form, block {s.block}, degree {s.degree}")
+    t0 = time.perf_counter()
+    r32 = P.pfe_solve_interval(s.h, s.lo, s.hi, s.block, s.block, degree=s.degree, tol=1e-8,
+                               x0=s.X0, precision=P.PFE_FP32)
+    t32 = time.perf_counter() - t0
+    st = r32["stats"]
+    mem = P.pfe_device_bytes(s.h)
+    banner(f"FP32 form {t32:.1f} s ({st['iterations'] - st['fp64_iterations']} FP32 iterations, "
+           f"one sweep of {st['refine_applications']} FP64 applications) against FP64 "
+           f"{r64['time']:.1f} s: {r64['time'] / t32:.2f}x; library device memory "
            f"{mem / 2**30:.1f} GiB")
-    assert n64 == n32
-    # each Ritz value lies within its residual (times lambda_ub) of an
-    # eigenvalue, so the two forms' values differ by at most the sum
-    diff = np.abs(r32["evals"] - r64["evals"])
-    banner(f"max relative eigenvalue difference FP32 form vs FP64: "
-           f"{(diff / r64['evals']).max():.3e}")
-    assert np.all(diff <= (r32["resid"] + r64["resid"]) * ub)
-    assert abs(n64 - gd["count_estimate"]) <= 4 * gd["count_stderr"] + 0.25 * gd["count_estimate"]
-    check_pairs(H, r64, ub, 1e-10, "FP64")
-    check_pairs(H, r32, ub, 1e-8, "FP32 form")
+    assert r32["status"] == "PFE_OK", st
+    assert st["refined"] == 1 and st["fp64_iterations"] == 1
+    assert r32["evals"].size == r64["evals"].size
+    rel = np.abs(r32["evals"] - r64["evals"]) / r64["evals"]
+    banner(f"max relative eigenvalue difference FP32 form vs FP64: {rel.max():.3e}")
+    assert rel.max() <= 1e-8
+    check_pairs(s.H, r32, s.ub, 1e-8, "FP32 form")
 
 
 def test_config_4m_largest_instance():

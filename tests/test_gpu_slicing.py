@@ -122,9 +122,12 @@ def test_sliced_degenerate_cluster_on_cut():
         P.pfe_destroy(h)
 
 
-def test_sliced_fp32_form(case):
-    """The FP32-filter form under slicing: FP32 iterations, then FP64 sweeps
-    until tol, slice by slice."""
+def test_sliced_fp32_form(case, monkeypatch):
+    """The FP32-filter form under slicing: FP32 iterations, then FP64
+    refinement sweeps, slice by slice (up to 8 per sub-window by default
+    under slicing, since splitting a sub-window does not help its
+    refinement)."""
+    monkeypatch.setenv("PFEIG_TRACE", "1")               # one line per outer iteration
     banner("sliced solve, FP32-filter form, 3 slices")
     out = P.pfe_solve_sliced(case.h, case.lo, case.hi, 40, 32, n_slices=3, tol=1e-10,
                              precision=P.PFE_FP32)

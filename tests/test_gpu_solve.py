@@ -54,9 +54,12 @@ def test_solve_fp64_matches_dense(case):
 def test_solve_fp64_matches_oracle_si(case):
     banner("solve fp64 vs oracle SI")
     X0 = gaussian_block(case.n, 32, 11)
+    # the oracle side designs its own filter (eq. transf.1, App. A, eq. thresh)
     c, e = F.spectral_map(0.0, case.ub)
-    f = P.pfe_design_filter(case.lo, case.hi, 0.0, case.ub, degree=80)
-    th, X, res, it = subspace.subspace_iteration(case.H, c, e, f.coef, X0, case.lo, case.hi,
+    xi, eta = (case.lo - c) / e, (case.hi - c) / e
+    eps = F.eps_rule(xi, eta, 80, 0.1 ** 0.25)
+    coef = F.filter_coefficients(xi, eta, eps, 80)
+    th, X, res, it = subspace.subspace_iteration(case.H, c, e, coef, X0, case.lo, case.hi,
                                                  case.ub, tol=1e-12)
     out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-10, x0=X0)
     np.testing.assert_allclose(out["evals"], th, rtol=1e-10)
@@ -125,19 +128,41 @@ def test_solve_fp32_form(case):
     assert out["stats"]["refined"] == 1
 
 
-def test_solve_fp32_form_refines_until_converged(case):
+def test_solve_fp32_form_one_sweep_far_below_the_floor(case):
     """A tolerance far below the FP32 rounding floor: the FP32 iterations
-    plateau, then FP64 refinement sweeps run until the residuals meet it."""
-    banner("solve fp32-filter form N=1000, tol 1e-12 (several FP64 sweeps)")
+    plateau, then exactly one FP64 refinement sweep runs, its filter applied
+    as often as the Ritz values' rate bound asks (orthonormalised between
+    applications).  It either meets tol or returns ENOCONV with only the
+    converged pairs; nothing runs after it."""
+    banner("solve fp32-filter form N=1000, tol 1e-12 (one FP64 sweep)")
     X0 = gaussian_block(case.n, 32, 11)
     out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=20, tol=1e-12,
-                               precision=P.PFE_FP32, x0=X0)
+                               precision=P.PFE_FP32, x0=X0, allow_noconv=True)
+    st = out["stats"]
+    assert st["refined"] == 1 and st["fp64_iterations"] == 1
+    assert 1 <= st["refine_applications"] <= 16
+    assert out["status"] in ("PFE_OK", "PFE_ENOCONV"), out["status"]
+    assert np.all(out["resid"] <= 1e-12)
+    ref, _ = dense.window(case.lam, case.U, case.lo, case.hi)
+    if out["status"] == "PFE_OK":
+        np.testing.assert_allclose(out["evals"], ref, rtol=1e-12)
+    else:
+        for lam in out["evals"]:
+            assert np.min(np.abs(ref - lam) / ref) <= 1e-12
+
+
+def test_solve_fp32_form_further_sweeps_are_opt_in(case):
+    """refine_sweeps > 1 lets the FP32 form run further FP64 sweeps, each
+    sized from the residual the previous one left, until tol is met."""
+    banner("solve fp32-filter form N=1000, tol 1e-12, up to 6 sweeps")
+    X0 = gaussian_block(case.n, 32, 11)
+    out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=20, tol=1e-12,
+                               precision=P.PFE_FP32, x0=X0, refine_sweeps=6)
     assert out["status"] == "PFE_OK", out["stats"]
     check_pairs(case, out, 1e-12, 1e-10)
     st = out["stats"]
-    assert st["refined"] >= 2
+    assert 1 <= st["refined"] <= 6
     assert st["fp64_iterations"] == st["refined"]
-    assert st["iterations"] > st["refined"]
 
 
 def test_solve_window_in_a_gap_returns_nothing(case):
@@ -177,3 +202,60 @@ def test_solve_bounds_too_small_is_detected(case):
         assert e.value.status == -7
     finally:
         P.pfe_set_bounds(case.h, 0.0, case.ub)
+
+
+def test_solve_rank_deficient_start_block(case):
+    """A start block with a zero column and a repeated one: the first
+    Cholesky factorisation breaks down, the shifted pass (shifted CholeskyQR)
+    runs, the repeated direction breaks down again and its column is refilled
+    with a Gaussian one, after which the solve matches dense LAPACK."""
+    banner("solve from a rank-deficient start block (shifted CholQR3 + refill)")
+    X0 = gaussian_block(case.n, 32, 11)
+    X0[:, 5] = 0.0
+    X0[:, 7] = X0[:, 6]
+    out = P.pfe_solve_interval(case.h, case.lo, case.hi, 40, 32, degree=80, tol=1e-10, x0=X0)
+    assert out["status"] == "PFE_OK", out["stats"]
+    assert out["stats"]["shifted_passes"] >= 2
+    check_pairs(case, out, 1e-10, 1e-9)
+
+
+def _gap_index(lam, i, span=12):
+    """Index j near i with the widest gap lam[j] - lam[j-1] (a window edge
+    between lam[j-1] and lam[j] then sits in a clear gap)."""
+    js = np.arange(max(1, i - span), min(lam.size - 1, i + span) + 1)
+    return int(js[np.argmax(lam[js] - lam[js - 1])])
+
+
+@pytest.fixture(scope="module")
+def wide():
+    banner("glass N=2197 (wide blocks; dense eigenvalues)")
+    c = GlassCase(2197, dense=False)
+    c.lam = np.linalg.eigvalsh(c.H.toarray())
+    c.h = c.handle()
+    _, c.ub, c.th = lanczos.lanczos_bounds(c.H, gaussian_vector(c.n, 7), 30)
+    P.pfe_set_bounds(c.h, 0.0, c.ub)
+    yield c
+    P.pfe_destroy(c.h)
+
+
+@pytest.mark.parametrize("q", [160, 256])
+def test_solve_wide_blocks_match_dense(wide, q):
+    """Blocks above 128 columns take the wide forms of every solver kernel:
+    the partial Gram products, the global-memory Cholesky inverse, the
+    global Jacobi eigensolver and the tall GEMM, all inside the subspace
+    iteration.  The window holds about 0.6 q eigenvalues, its ends in gaps."""
+    lam = wide.lam
+    i0 = _gap_index(lam, int(np.searchsorted(lam, 0.02 * lam[-1])))
+    i1 = _gap_index(lam, i0 + int(0.6 * q))
+    lo, hi = 0.5 * (lam[i0 - 1] + lam[i0]), 0.5 * (lam[i1 - 1] + lam[i1])
+    want = lam[i0:i1]
+    banner(f"solve fp64 N=2197 q={q}: {want.size} eigenvalues")
+    X0 = gaussian_block(wide.n, q, 11)
+    out = P.pfe_solve_interval(wide.h, lo, hi, q, q, degree=100, tol=1e-10, x0=X0)
+    assert out["status"] == "PFE_OK", out["stats"]
+    assert out["evals"].shape == want.shape
+    assert np.max(np.abs(out["evals"] - want) / want) <= 1e-10
+    V = np.ascontiguousarray(out["evecs"].T)
+    res = np.linalg.norm(wide.H @ V - V * out["evals"][None, :], axis=0) / wide.ub
+    assert res.max() <= 1e-9
+    assert np.abs(V.T @ V - np.eye(V.shape[1])).max() <= 1e-10

@@ -487,23 +487,27 @@ hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev,
   if (chunk <= 0 || chunk > per_xcd) chunk = (int)per_xcd;
   const int64_t grid_x = ((nblk + 8LL * chunk - 1) / (8LL * chunk)) * 8LL * chunk;
   if (pass_w <= 0 || pass_w > 64 * NP * VW || pass_w % VW) return hipErrorInvalidValue;
-  dim3 grid((unsigned)grid_x, (unsigned)((q + pass_w - 1) / pass_w));
+  const int npass = (q + pass_w - 1) / pass_w;
+  dim3 grid((unsigned)grid_x, (unsigned)npass);
   // tile kernels: out = alpha acc, acc started from prev and add scaled by
   // 1/alpha (quotients rounded once, from the double values)
   const double sa = alpha != T(0) ? (double)alpha : 1.0;
   const T cb = (T)((double)beta / sa), cd = (T)((double)delta / sa), cz = (T)((double)zeta / sa);
+  // FP64 tiles of more than two rows take one record per batch: a batch's
+  // block values (U R 9 doubles) stay within the scalar registers.
+  constexpr int U34 = sizeof(T) == 8 ? 1 : kTileUnroll;
   if (R == 2) {
     hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 2>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
                        A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
                        chunk);
   } else if (R == 3) {
-    hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 3>), grid, dim3(256), 0, s,
+    hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, U34, 3>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
                        A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
                        chunk);
   } else if (R == 4) {
-    hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 4>), grid, dim3(256), 0, s,
+    hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, U34, 4>), grid, dim3(256), 0, s,
                        (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
                        A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
                        chunk);

@@ -10,6 +10,13 @@ benchmark times.
   recomputed on the CPU;
 * the filter adjoint against the oracle at a small degree, and the
   self-adjointness of p(H_hat) at the benchmark's degree 150;
+* the differentiation form at its own size (block 64, degree 150, window
+  [0.5 %, 1.5 %] theta_max): the gradient in 50 spring constants through
+  torch.autograd, with ceil(sqrt d)-step checkpoints and with the resident
+  trajectories, against the oracle's central differences (step 1e-6) stored
+  in golden/glass100k_cfg4_fd.json (written by golden/make_cfg4_fd.py); the
+  block gradient of the two modes bit for bit and against the oracle's
+  reverse mode on sampled blocks;
 * the Hellmann-Feynman gradient and the spring chain rule of found
   eigenvectors against the oracle.
 """
@@ -29,6 +36,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN_PATH = os.path.join(os.path.dirname(__file__), "golden", "glass100k_window.json")
 GOLDEN = json.load(open(GOLDEN_PATH)) if os.path.exists(GOLDEN_PATH) else None
+FD_PATH = os.path.join(os.path.dirname(__file__), "golden", "glass100k_cfg4_fd.json")
 
 
 class Full:
@@ -127,6 +135,67 @@ def test_full_adjoint_self_adjoint_d150(full):
     dX, _ = P.pfe_apply_filter_adjoint(full.h, f, X, W, full.g.nnzb, 0)
     # p(H_hat) is symmetric, so the input gradient is the filter applied to dY
     assert rel_err(dX, P.pfe_apply_filter(full.h, f, W)) <= 1e-12
+
+
+def _fd_case(full):
+    fd = json.load(open(FD_PATH))
+    assert fd["n_atoms"] == full.g.n_atoms and fd["seed"] == GOLDEN["seed"]
+    assert len(fd["fd"]) == fd["n_sample"] == 50
+    f = P.Filter(fd["degree"], P.PFE_SMOOTH_NONE, fd["c"], fd["e"], fd["xi"], fd["eta"], fd["eps"],
+                 np.asarray(fd["coef"]))
+    X = gaussian_block(full.n, fd["block"], fd["x_seed"])
+    W = gaussian_block(full.n, fd["block"], fd["w_seed"])
+    return fd, f, X, W
+
+
+def test_full_differentiation_form_vs_central_differences(full):
+    """Differentiation configuration: L = <W, p(H_hat) X> at block 64 and
+    degree 150, its gradient in every spring constant through the autograd
+    chain (spring assembly, filter, adjoint, chain rule), against the
+    oracle's central differences on 50 springs, in the checkpointed mode
+    (13-step segments) and with the resident trajectories."""
+    import torch
+    from paper_1902_07041_amd.autograd import SpringSystem
+    fd, f, X, W = _fd_case(full)
+    g = full.g
+    idx = np.asarray(fd["springs"])
+    ref = np.asarray(fd["fd"])
+    Xt, Wt = torch.from_numpy(X).cuda(), torch.from_numpy(W).cuda()
+    with SpringSystem(g.row_ptr, g.col_idx, g.pairs, g.unit) as sysm:
+        for stride, resident in ((13, False), (0, True)):
+            banner(f"differentiation form q=64 d=150: autograd dk vs central differences "
+                   f"(stride {stride}, resident {resident})")
+            k = torch.from_numpy(g.k).cuda().requires_grad_()
+            m = torch.from_numpy(g.masses).cuda().requires_grad_()
+            H = sysm.assemble(k, m)
+            loss = (Wt * sysm.filter(Xt, H, f, ckpt_stride=stride, resident=resident)).sum()
+            loss.backward()
+            dk = k.grad.cpu().numpy()[idx]
+            err = np.linalg.norm(dk - ref) / np.linalg.norm(ref)
+            banner(f"relative error over the 50 springs {err:.3e}")
+            assert err <= 1e-6
+
+
+def test_full_adjoint_d150_modes_and_block_sample(full):
+    """Block gradient at block 64, degree 150: the checkpointed sweep (the
+    default), an explicit stride of 13 and the resident trajectories give
+    identical bits; 40 sampled blocks and dX match the oracle's reverse mode."""
+    fd, f, X, W = _fd_case(full)
+    banner("adjoint q=64 d=150: checkpoints vs resident, and the oracle on sampled blocks")
+    dX0, dB0 = P.pfe_apply_filter_adjoint(full.h, f, X, W, full.g.nnzb, 0)
+    dX1, dB1 = P.pfe_apply_filter_adjoint(full.h, f, X, W, full.g.nnzb, 13)
+    dX2, dB2 = P.pfe_apply_filter_adjoint(full.h, f, X, W, full.g.nnzb, 0, resident=True)
+    np.testing.assert_array_equal(dX0, dX1)
+    np.testing.assert_array_equal(dB0, dB1)
+    np.testing.assert_array_equal(dX0, dX2)
+    np.testing.assert_array_equal(dB0, dB2)
+    pick = np.random.default_rng(19).choice(full.g.nnzb, 40, replace=False)
+    Hhat = cbsr.BsrOperator(full.g.row_ptr, full.g.col_idx,
+                            hessian.mapped_blocks(full.g.row_ptr, full.g.col_idx, full.hb, f.c, f.e))
+    rX, rG = adjoint.filter_vjp_block_sample(Hhat.__matmul__, f.e, f.coef, X, W, full.g.row_ptr,
+                                             full.g.col_idx, pick)
+    assert rel_err(dX0, rX) <= 1e-12
+    assert rel_err(dB0[pick], rG) <= 1e-10
 
 
 def test_full_hellmann_feynman(full):

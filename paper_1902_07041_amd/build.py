@@ -20,6 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpfeig.so")
 SOURCES = ["api.hip", "k_sparse.hip", "k_dense.hip", "k_adjoint.hip", "filter_design.cpp",
+           "lanczos_host.cpp",
            "reorder.cpp"]
 ARCH = "gfx950"
 

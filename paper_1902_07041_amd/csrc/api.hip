@@ -12,10 +12,12 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
 #include "internal.h"
+#include "lanczos_host.h"
 
 using pfe::DevBuf;
 using pfe::Err;
@@ -145,6 +147,33 @@ namespace {
 pfe_status finish(pfe_handle h, const Err& e) {
   if (h) h->err = e.st == PFE_OK ? std::string() : e.msg;
   return e.st;
+}
+
+// No C++ exception crosses the C-ABI: a failed host allocation (std::bad_alloc)
+// becomes PFE_ENOMEM, anything else PFE_EHIP, each with a message.
+template <class F>
+pfe_status guarded(pfe_handle h, F&& body) {
+  try {
+    return finish(h, body());
+  } catch (const std::bad_alloc&) {
+    return finish(h, pfe::fail(PFE_ENOMEM, "host allocation failed"));
+  } catch (const std::exception& ex) {
+    return finish(h, pfe::fail(PFE_EHIP, std::string("internal error: ") + ex.what()));
+  } catch (...) {
+    return finish(h, pfe::fail(PFE_EHIP, "internal error"));
+  }
+}
+
+// The same for entry points without a handle.
+template <class F>
+pfe_status host_guarded(F&& body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return PFE_ENOMEM;
+  } catch (...) {
+    return PFE_EHIP;
+  }
 }
 
 Err select_device(pfe_handle h) {
@@ -586,7 +615,8 @@ pfe_status pfe_create(int device, void* hip_stream, pfe_handle* out) {
   if (device < 0 || device >= ndev)
     return create_fail(nullptr, PFE_EINVAL,
                        "device " + std::to_string(device) + " out of range (" + std::to_string(ndev) + " devices)");
-  pfe_ctx* h = new pfe_ctx();
+  pfe_ctx* h = new (std::nothrow) pfe_ctx();
+  if (!h) return create_fail(nullptr, PFE_ENOMEM, "host allocation failed");
   h->device = device;
   if ((e = hipSetDevice(device)) != hipSuccess)
     return create_fail(h, PFE_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
@@ -799,7 +829,7 @@ pfe_status pfe_set_hessian(pfe_handle h, int64_t n_atoms, int64_t nnzb, const in
                            const int32_t* col_idx, const double* blocks, const double* masses,
                            uint32_t flags) {
   if (!h) return PFE_EINVAL;
-  return finish(h, set_hessian_impl(h, n_atoms, nnzb, row_ptr, col_idx, blocks, masses, flags));
+  return guarded(h, [&] { return set_hessian_impl(h, n_atoms, nnzb, row_ptr, col_idx, blocks, masses, flags); });
 }
 
 // Spring network: K assembled on the device, then the same import as above.
@@ -877,8 +907,8 @@ pfe_status pfe_set_springs(pfe_handle h, int64_t n_atoms, int64_t nnzb, const in
                            const double* unit, const double* k, const double* masses,
                            double* hblocks_out, uint32_t flags) {
   if (!h) return PFE_EINVAL;
-  return finish(h, set_springs_impl(h, n_atoms, nnzb, row_ptr, col_idx, n_springs, pairs, unit, k,
-                                    masses, hblocks_out, flags));
+  return guarded(h, [&] { return set_springs_impl(h, n_atoms, nnzb, row_ptr, col_idx, n_springs, pairs, unit, k,
+                                    masses, hblocks_out, flags); });
 }
 
 // ----------------------------------------------------------------- bounds
@@ -967,7 +997,7 @@ static Err bounds_impl(pfe_handle h, int m, const double* v0, uint64_t seed, uin
 pfe_status pfe_estimate_bounds(pfe_handle h, int32_t steps, const double* v0, uint64_t seed,
                                uint32_t flags, double* lam_lb, double* lam_ub, double* theta_max) {
   if (!h) return PFE_EINVAL;
-  return finish(h, bounds_impl(h, steps, v0, seed, flags, lam_lb, lam_ub, theta_max));
+  return guarded(h, [&] { return bounds_impl(h, steps, v0, seed, flags, lam_lb, lam_ub, theta_max); });
 }
 
 pfe_status pfe_set_bounds(pfe_handle h, double lam_lb, double lam_ub) {
@@ -984,23 +1014,25 @@ pfe_status pfe_set_bounds(pfe_handle h, double lam_lb, double lam_ub) {
 pfe_status pfe_design_filter(double lam_lo, double lam_hi, double lam_lb, double lam_ub,
                              const pfe_filter_opts* opts, double* coef_out, int32_t coef_cap,
                              pfe_filter* out) {
-  if (!opts || !out) return PFE_EINVAL;
-  pfe::FilterDesign f;
-  Err e = pfe::design_filter(lam_lo, lam_hi, lam_lb, lam_ub, opts->degree, opts->eps, opts->r,
-                             opts->smoothing, &f);
-  if (e) return e.st;
-  out->degree = f.degree;
-  out->smoothing = f.smoothing;
-  out->c = f.c;
-  out->e = f.e;
-  out->xi = f.xi;
-  out->eta = f.eta;
-  out->eps = f.eps;
-  out->coef = nullptr;
-  if (!coef_out || coef_cap < f.degree + 1) return PFE_ECAPACITY;
-  std::memcpy(coef_out, f.coef.data(), (f.degree + 1) * sizeof(double));
-  out->coef = coef_out;
-  return PFE_OK;
+  return host_guarded([&]() -> pfe_status {
+    if (!opts || !out) return PFE_EINVAL;
+    pfe::FilterDesign f;
+    Err e = pfe::design_filter(lam_lo, lam_hi, lam_lb, lam_ub, opts->degree, opts->eps, opts->r,
+                               opts->smoothing, &f);
+    if (e) return e.st;
+    out->degree = f.degree;
+    out->smoothing = f.smoothing;
+    out->c = f.c;
+    out->e = f.e;
+    out->xi = f.xi;
+    out->eta = f.eta;
+    out->eps = f.eps;
+    out->coef = nullptr;
+    if (!coef_out || coef_cap < f.degree + 1) return PFE_ECAPACITY;
+    std::memcpy(coef_out, f.coef.data(), (f.degree + 1) * sizeof(double));
+    out->coef = coef_out;
+    return PFE_OK;
+  });
 }
 
 // ----------------------------------------------------------- apply_filter
@@ -1044,7 +1076,7 @@ static Err apply_impl(pfe_handle h, const pfe_filter* f, int nvec, const void* X
 pfe_status pfe_apply_filter(pfe_handle h, const pfe_filter* f, int32_t nvec, const void* X,
                             void* Y, int64_t ld, int32_t precision, uint32_t flags) {
   if (!h) return PFE_EINVAL;
-  return finish(h, apply_impl(h, f, nvec, X, Y, ld, precision, flags));
+  return guarded(h, [&] { return apply_impl(h, f, nvec, X, Y, ld, precision, flags); });
 }
 
 // The FP64 filter of apply_impl on device arrays with the recurrence's
@@ -1073,7 +1105,7 @@ static Err apply_noalloc_impl(pfe_handle h, const pfe_filter* f, int nvec, const
 pfe_status pfe_apply_filter_noalloc(pfe_handle h, const pfe_filter* f, int32_t nvec,
                                     const double* X, double* Y, int64_t ld) {
   if (!h) return PFE_EINVAL;
-  return finish(h, apply_noalloc_impl(h, f, nvec, X, Y, ld));
+  return guarded(h, [&] { return apply_noalloc_impl(h, f, nvec, X, Y, ld); });
 }
 
 // ------------------------------------------------------------------ solve
@@ -1415,7 +1447,7 @@ pfe_status pfe_solve_interval(pfe_handle h, double lam_lo, double lam_hi, int32_
                               const pfe_solve_opts* opts, int32_t* n_found, double* evals,
                               double* evecs, double* resid, pfe_solve_stats* stats) {
   if (!h) return PFE_EINVAL;
-  return finish(h, solve_impl(h, lam_lo, lam_hi, nev, opts, n_found, evals, evecs, resid, stats));
+  return guarded(h, [&] { return solve_impl(h, lam_lo, lam_hi, nev, opts, n_found, evals, evecs, resid, stats); });
 }
 
 // ------------------------------------------------------------------ count
@@ -1468,8 +1500,8 @@ pfe_status pfe_estimate_count(pfe_handle h, double lam_lo, double lam_hi, int32_
                               int32_t smoothing, int32_t nsamples, const double* V, uint64_t seed,
                               uint32_t flags, double* count) {
   if (!h) return PFE_EINVAL;
-  return finish(h, count_impl(h, lam_lo, lam_hi, degree, smoothing, nsamples, V, seed, flags,
-                              count));
+  return guarded(h, [&] { return count_impl(h, lam_lo, lam_hi, degree, smoothing, nsamples, V, seed, flags,
+                              count); });
 }
 
 // ---------------------------------------------------------------- moments
@@ -1545,10 +1577,12 @@ pfe_status pfe_count_moments(pfe_handle h, int32_t K, int32_t nsamples, const do
                              uint64_t seed, uint32_t flags, double* mu) {
   if (!h) return PFE_EINVAL;
   if (!mu) return finish(h, pfe::fail(PFE_EINVAL, "mu output required"));
-  std::vector<double> m;
-  Err e = moments_impl(h, K, nsamples, V, seed, flags, &m);
-  if (e.st == PFE_OK) std::copy(m.begin(), m.end(), mu);
-  return finish(h, e);
+  return guarded(h, [&] {
+    std::vector<double> m;
+    Err e = moments_impl(h, K, nsamples, V, seed, flags, &m);
+    if (e.st == PFE_OK) std::copy(m.begin(), m.end(), mu);
+    return e;
+  });
 }
 
 // ---------------------------------------------------------------- slicing
@@ -1843,8 +1877,8 @@ pfe_status pfe_solve_sliced(pfe_handle h, double lam_lo, double lam_hi, int32_t 
                             int32_t* n_slices, double* cuts, int32_t cuts_cap,
                             pfe_solve_stats* stats) {
   if (!h) return PFE_EINVAL;
-  return finish(h, sliced_impl(h, lam_lo, lam_hi, nev, opts, slice_opts, n_found, evals, evecs,
-                               resid, n_slices, cuts, cuts_cap, stats));
+  return guarded(h, [&] { return sliced_impl(h, lam_lo, lam_hi, nev, opts, slice_opts, n_found, evals, evecs,
+                               resid, n_slices, cuts, cuts_cap, stats); });
 }
 
 // ------------------------------------------------------ thick-restart Lanczos
@@ -1875,9 +1909,11 @@ static Err lanczos_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   const int b = o.block;
   if (b < 1 || b > 64) return pfe::fail(PFE_EINVAL, "block must be in [1, 64]");
   if (nev < 0 || !n_found) return pfe::fail(PFE_EINVAL, "nev >= 0 and n_found required");
-  int m = o.max_basis > 0 ? o.max_basis : (int)std::max<int64_t>(4 * b, 3 * (int64_t)std::max(nev, 1));
-  m = (int)round_up(m, b);
-  if (m + b > 511 || m < 3 * b) return pfe::fail(PFE_EINVAL, "max_basis must give 3 block <= m and m + block <= 511");
+  const int64_t m_req = o.max_basis > 0 ? (int64_t)o.max_basis : std::max<int64_t>(4 * b, 3 * (int64_t)std::max(nev, 1));
+  pfe::LanczosShape shp;
+  if (m_req > 511 || pfe::lanczos_shape((int)round_up(m_req, b), b, &shp) != 0)
+    return pfe::fail(PFE_EINVAL, "max_basis must give 3 block <= m and m + block <= 511");
+  const int m = shp.m;
   if (m + b > n) return pfe::fail(PFE_EINVAL, "basis larger than the matrix");
   if (lam_lo < h->lam_lb || lam_hi > h->lam_ub)
     return pfe::fail(PFE_EINVAL, "window must lie inside [lam_lb, lam_ub]");
@@ -1942,9 +1978,11 @@ static Err lanczos_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     Timer tm(h, &st.t_orth);
     PFE_TRY(orth_block(V, 0, V));
   }
-  const int M1 = m + b;
+  const int M1 = shp.M1;
   std::vector<double> T((size_t)M1 * M1, 0.0), Cf((size_t)M1 * b), th(m), Q((size_t)m * m);
-  std::vector<double> Tm((size_t)m * m);
+  std::vector<double> Tm((size_t)m * m), rA(m), Mh;
+  // host matrices copied into sm.Rinv (2 (m + b)^2 doubles)
+  const size_t rinv_cap = 2 * (size_t)M1 * M1;
   int p = b;                       // columns [p - b, p) still need their filtered image
   double epsA = 0.1 * tol;         // A-residual target relative to rho(gamma)
   int prev_nw = -1, cycles = 0, tightened = 0;
@@ -1973,17 +2011,12 @@ static Err lanczos_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
                                hipMemcpyDeviceToHost, h->stream));
         PFE_TRY(sync(h));
       }
-      for (int r = 0; r < p + b; ++r)
-        for (int c = 0; c < b; ++c) {
-          const double v = Cf[(size_t)r * b + c];
-          T[(size_t)r * M1 + (p - b + c)] = v;
-          T[(size_t)(p - b + c) * M1 + r] = v;
-        }
+      if (pfe::lanczos_store_block(shp, p, Cf, T) != 0)
+        return pfe::fail(PFE_EHIP, "internal: Lanczos Gram block outside T");
       p += b;
     }
     // ---- Ritz pairs of T_m (device Jacobi)
-    for (int r = 0; r < m; ++r)
-      for (int c = 0; c < m; ++c) Tm[(size_t)r * m + c] = T[(size_t)r * M1 + c];
+    if (pfe::lanczos_leading(shp, T, Tm) != 0) return pfe::fail(PFE_EHIP, "internal: Lanczos T shape");
     int info = 0;
     {
       Timer tm(h, &st.t_rr);
@@ -1998,22 +2031,15 @@ static Err lanczos_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     ++cycles;
     st.iterations = cycles;
     // residual norms ||B s_i||, B = T[m:m+b, m-b:m]
-    std::vector<double> rA(m, 0.0);
-    for (int i = 0; i < m; ++i) {
-      double s2 = 0;
-      for (int a = 0; a < b; ++a) {
-        double v = 0;
-        for (int r = 0; r < b; ++r) v += T[(size_t)(m + a) * M1 + (m - b + r)] * Q[(size_t)(m - b + r) * m + i];
-        s2 += v * v;
-      }
-      rA[i] = std::sqrt(s2);
-    }
+    if (pfe::lanczos_ritz_residuals(shp, T, Q, rA) != 0)
+      return pfe::fail(PFE_EHIP, "internal: Lanczos residual shape");
     // wanted: theta >= tau, largest first (theta ascending from Jacobi)
     std::vector<int> want;
     for (int i = m - 1; i >= 0; --i)
       if (th[i] >= dd.tau) want.push_back(i);
     const int nw = (int)want.size();
-    if (nw > m - 2 * b) {
+    const int k = pfe::lanczos_keep(shp, nw);
+    if (k < 0) {
       *n_found = nw;
       return pfe::fail(PFE_ECAPACITY, "max_basis too small for the eigenvalues above tau");
     }
@@ -2033,10 +2059,10 @@ static Err lanczos_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
         done = true;
         break;
       }
-      std::vector<double> Mw((size_t)m * nw);
-      for (int r = 0; r < m; ++r)
-        for (int c = 0; c < nw; ++c) Mw[(size_t)r * nw + c] = Q[(size_t)r * m + want[c]];
-      PFE_HIP(hipMemcpyAsync(sm.Rinv, Mw.data(), Mw.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+      if (pfe::lanczos_select_columns(shp, Q, want, Mh) != 0 || Mh.size() > rinv_cap)
+        return pfe::fail(PFE_EHIP, "internal: Lanczos wanted columns");
+      PFE_HIP(hipMemcpyAsync(sm.Rinv, Mh.data(), Mh.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+      PFE_TRY(sync(h));
       PFE_HIP(pfe::gemm_tall_f64(n, m, nw, V, ldv, sm.Rinv, Scr, ldv, h->stream));
       {
         Timer tm(h, &st.t_orth);
@@ -2057,23 +2083,16 @@ static Err lanczos_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
     if (cycles >= max_restarts) return pfe::fail(PFE_ENOCONV, "not converged within max_restarts");
     // ---- thick restart: keep the k largest Ritz vectors, k a multiple of b
     // so that the expansion fills the basis exactly up to m + b columns
-    const int k = std::min(m - b, (int)round_up(std::max(nw + b, 2 * b), b));
-    std::vector<double> Mk((size_t)m * k);
-    for (int r = 0; r < m; ++r)
-      for (int c = 0; c < k; ++c) Mk[(size_t)r * k + c] = Q[(size_t)r * m + (m - 1 - c)];
-    PFE_HIP(hipMemcpyAsync(sm.Rinv, Mk.data(), Mk.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    std::vector<int> keep(k);
+    for (int c = 0; c < k; ++c) keep[c] = m - 1 - c;
+    if (pfe::lanczos_select_columns(shp, Q, keep, Mh) != 0 || Mh.size() > rinv_cap)
+      return pfe::fail(PFE_EHIP, "internal: Lanczos kept columns");
+    PFE_HIP(hipMemcpyAsync(sm.Rinv, Mh.data(), Mh.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
     PFE_HIP(pfe::gemm_tall_f64(n, m, k, V, ldv, sm.Rinv, V, ldv, h->stream));
     PFE_HIP(pfe::copy_cols_f64(n, b, V + m, ldv, V + k, ldv, h->stream));
-    std::vector<double> Tn((size_t)M1 * M1, 0.0);
-    for (int c = 0; c < k; ++c) Tn[(size_t)c * M1 + c] = th[m - 1 - c];
-    for (int a = 0; a < b; ++a)
-      for (int c = 0; c < k; ++c) {
-        double v = 0;
-        for (int r = 0; r < b; ++r) v += T[(size_t)(m + a) * M1 + (m - b + r)] * Q[(size_t)(m - b + r) * m + (m - 1 - c)];
-        Tn[(size_t)(k + a) * M1 + c] = v;
-        Tn[(size_t)c * M1 + (k + a)] = v;
-      }
-    T.swap(Tn);
+    PFE_TRY(sync(h));
+    if (pfe::lanczos_restart(shp, k, th, Q, T) != 0)
+      return pfe::fail(PFE_EHIP, "internal: Lanczos restart shape");
     p = k + b;
   }
   // ---- selection and output (theta ascending)
@@ -2133,48 +2152,52 @@ pfe_status pfe_solve_lanczos(pfe_handle h, double lam_lo, double lam_hi, int32_t
                              const pfe_lanczos_opts* opts, int32_t* n_found, double* evals,
                              double* evecs, double* resid, pfe_solve_stats* stats) {
   if (!h) return PFE_EINVAL;
-  return finish(h, lanczos_impl(h, lam_lo, lam_hi, nev, opts, n_found, evals, evecs, resid, stats));
+  return guarded(h, [&] { return lanczos_impl(h, lam_lo, lam_hi, nev, opts, n_found, evals, evecs, resid, stats); });
 }
 
 pfe_status pfe_locality_order(int64_t n_atoms, int64_t nnzb, const int64_t* row_ptr,
                               const int32_t* col_idx, int32_t leaf, int32_t group, int64_t window,
                               int32_t* order, double* far_in, double* far_out) {
-  if (n_atoms <= 0 || n_atoms > (int64_t)INT32_MAX || nnzb < 0 || !row_ptr || !col_idx ||
-      !order || group < 1 || group > 4 || leaf < 2 * group || window < 0)
-    return PFE_EINVAL;
-  if (row_ptr[0] != 0 || row_ptr[n_atoms] != nnzb) return PFE_EINVAL;
-  for (int64_t i = 0; i < n_atoms; ++i)
-    if (row_ptr[i + 1] < row_ptr[i]) return PFE_EINVAL;
-  for (int64_t k = 0; k < nnzb; ++k)
-    if (col_idx[k] < 0 || col_idx[k] >= n_atoms) return PFE_EINVAL;
-  std::vector<int32_t> ord;
-  pfe::locality_order(n_atoms, row_ptr, col_idx, leaf, group, ord);
-  std::memcpy(order, ord.data(), (size_t)n_atoms * sizeof(int32_t));
-  if (far_in) *far_in = pfe::far_block_fraction(n_atoms, row_ptr, col_idx, nullptr, window);
-  if (far_out) *far_out = pfe::far_block_fraction(n_atoms, row_ptr, col_idx, ord.data(), window);
-  return PFE_OK;
+  return host_guarded([&]() -> pfe_status {
+    if (n_atoms <= 0 || n_atoms > (int64_t)INT32_MAX || nnzb < 0 || !row_ptr || !col_idx ||
+        !order || group < 1 || group > 4 || leaf < 2 * group || window < 0)
+      return PFE_EINVAL;
+    if (row_ptr[0] != 0 || row_ptr[n_atoms] != nnzb) return PFE_EINVAL;
+    for (int64_t i = 0; i < n_atoms; ++i)
+      if (row_ptr[i + 1] < row_ptr[i]) return PFE_EINVAL;
+    for (int64_t k = 0; k < nnzb; ++k)
+      if (col_idx[k] < 0 || col_idx[k] >= n_atoms) return PFE_EINVAL;
+    std::vector<int32_t> ord;
+    pfe::locality_order(n_atoms, row_ptr, col_idx, leaf, group, ord);
+    std::memcpy(order, ord.data(), (size_t)n_atoms * sizeof(int32_t));
+    if (far_in) *far_in = pfe::far_block_fraction(n_atoms, row_ptr, col_idx, nullptr, window);
+    if (far_out) *far_out = pfe::far_block_fraction(n_atoms, row_ptr, col_idx, ord.data(), window);
+    return PFE_OK;
+  });
 }
 
 pfe_status pfe_design_dirac(double lam_lo, double lam_hi, double lam_lb, double lam_ub,
                             int32_t degree, double phi, int32_t smoothing, double* coef_out,
                             int32_t coef_cap, pfe_dirac_filter* out) {
-  if (!out) return PFE_EINVAL;
-  pfe::DiracDesign dd;
-  const Err e = pfe::design_dirac(lam_lo, lam_hi, lam_lb, lam_ub, degree, phi, smoothing, &dd);
-  if (e) return e.st;
-  out->degree = dd.degree;
-  out->smoothing = dd.smoothing;
-  out->c = dd.c;
-  out->e = dd.e;
-  out->xi = dd.xi;
-  out->eta = dd.eta;
-  out->gamma = dd.gamma;
-  out->tau = dd.tau;
-  out->peak = dd.peak;
-  out->coef = coef_out;
-  if (!coef_out || coef_cap < dd.degree + 1) return PFE_ECAPACITY;
-  std::copy(dd.coef.begin(), dd.coef.end(), coef_out);
-  return PFE_OK;
+  return host_guarded([&]() -> pfe_status {
+    if (!out) return PFE_EINVAL;
+    pfe::DiracDesign dd;
+    const Err e = pfe::design_dirac(lam_lo, lam_hi, lam_lb, lam_ub, degree, phi, smoothing, &dd);
+    if (e) return e.st;
+    out->degree = dd.degree;
+    out->smoothing = dd.smoothing;
+    out->c = dd.c;
+    out->e = dd.e;
+    out->xi = dd.xi;
+    out->eta = dd.eta;
+    out->gamma = dd.gamma;
+    out->tau = dd.tau;
+    out->peak = dd.peak;
+    out->coef = coef_out;
+    if (!coef_out || coef_cap < dd.degree + 1) return PFE_ECAPACITY;
+    std::copy(dd.coef.begin(), dd.coef.end(), coef_out);
+    return PFE_OK;
+  });
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -2406,7 +2429,7 @@ pfe_status pfe_apply_filter_adjoint(pfe_handle h, const pfe_filter* f, int32_t n
                                     double* dblocks, int64_t ld, int32_t ckpt_stride,
                                     uint32_t flags) {
   if (!h) return PFE_EINVAL;
-  return finish(h, adjoint_impl(h, f, nvec, X, dY, dX, dblocks, ld, ckpt_stride, flags));
+  return guarded(h, [&] { return adjoint_impl(h, f, nvec, X, dY, dX, dblocks, ld, ckpt_stride, flags); });
 }
 
 // ----------------------------------------------------- gradient helpers
@@ -2448,7 +2471,7 @@ static Err eigvec_grad_impl(pfe_handle h, int nvec, const double* V, const doubl
 pfe_status pfe_eigvec_block_gradient(pfe_handle h, int32_t nvec, const double* V, const double* w,
                                      double* dblocks, uint32_t flags) {
   if (!h) return PFE_EINVAL;
-  return finish(h, eigvec_grad_impl(h, nvec, V, w, dblocks, flags));
+  return guarded(h, [&] { return eigvec_grad_impl(h, nvec, V, w, dblocks, flags); });
 }
 
 static Err spring_grad_impl(pfe_handle h, int64_t P, const int64_t* pairs, const double* unit,
@@ -2507,7 +2530,7 @@ pfe_status pfe_spring_gradient(pfe_handle h, int64_t n_springs, const int64_t* p
                                const double* unit, const double* dblocks, double* dk, double* dm,
                                uint32_t flags) {
   if (!h) return PFE_EINVAL;
-  return finish(h, spring_grad_impl(h, n_springs, pairs, unit, dblocks, dk, dm, flags));
+  return guarded(h, [&] { return spring_grad_impl(h, n_springs, pairs, unit, dblocks, dk, dm, flags); });
 }
 
 }  // extern "C"

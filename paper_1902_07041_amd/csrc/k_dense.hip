@@ -5,6 +5,8 @@
 // counter-based Gaussian generator and small Lanczos helpers.  All
 // reductions are two-pass and in a fixed order (no floating-point atomics),
 // so repeated runs are bitwise identical.
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace pfe {
@@ -187,6 +189,121 @@ __global__ __launch_bounds__(256) void k_gram_small(int64_t n, int q1, int q2,
       }
 }
 
+// Gram for 128 < max(q1, q2) <= 256: a work-group forms one 128 x 128 tile
+// (tm, tn) of G over a contiguous row range, wave w its 64 x 64 quarter as
+// 4 x 4 MFMA tiles; rows are staged 16 at a time through LDS, the next 16
+// loaded into registers meanwhile.  Work-group b runs on XCD b % 8; the T
+// tiles of one row range take consecutive ids on the same XCD (b, b + 8, ...),
+// so they stream the same rows together and share them through that XCD's
+// L2.  With A = B (sym) only tiles tm <= tn are formed, and an off-diagonal
+// tile is also written transposed.  Partial tiles go to work[split][q1][q2].
+constexpr int kGramRtTile = 128, kGramRtRows = 16;
+
+__global__ __launch_bounds__(256, 2) void k_gram_rt(int64_t n, int q1, int q2,
+                                                    const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ B, int64_t ldb,
+                                                    int64_t rows_per_split, int nsplit, int tiles_n,
+                                                    int ntiles, int sym, double* __restrict__ work) {
+  constexpr int TT = kGramRtTile, KR = kGramRtRows;
+  constexpr int L = KR * TT / 256;   // 8 per thread and operand
+  __shared__ double sA[KR][TT + 2];
+  __shared__ double sB[KR][TT + 2];
+  const int b = blockIdx.x, xcd = b & 7, s8 = b >> 3;
+  const int split = (s8 / ntiles) * 8 + xcd, tile = s8 % ntiles;
+  if (split >= nsplit) return;
+  int tm, tn;
+  if (sym) {   // upper-triangle tiles in row order
+    tm = 0;
+    int t = tile;
+    while (t >= tiles_n - tm) {
+      t -= tiles_n - tm;
+      ++tm;
+    }
+    tn = tm + t;
+  } else {
+    tm = tile / tiles_n;
+    tn = tile % tiles_n;
+  }
+  const int m0 = tm * TT, n0 = tn * TT;
+  const int64_t r_begin = (int64_t)split * rows_per_split;
+  const int64_t r_end = min(n, r_begin + rows_per_split);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4(0.0);
+  double ra[L], rb[L];
+  auto fetch = [&](int64_t rr0) {
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int idx = tid + 256 * t, rr = idx / TT, c = idx % TT;
+      const int64_t r = rr0 + rr;
+      ra[t] = (r < r_end && m0 + c < q1) ? A[r * lda + m0 + c] : 0.0;
+      rb[t] = (r < r_end && n0 + c < q2) ? B[r * ldb + n0 + c] : 0.0;
+    }
+  };
+  if (r_begin < r_end) fetch(r_begin);
+  for (int64_t rr0 = r_begin; rr0 < r_end; rr0 += KR) {
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int idx = tid + 256 * t;
+      sA[idx / TT][idx % TT] = ra[t];
+      sB[idx / TT][idx % TT] = rb[t];
+    }
+    __syncthreads();
+    if (rr0 + KR < r_end) fetch(rr0 + KR);
+#pragma unroll
+    for (int kk = 0; kk < KR; kk += 4) {
+      const int k = kk + (lane >> 4);
+      double a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sA[k][wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = sB[k][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(a[i], bb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  double* out = work + (int64_t)split * q1 * q2;
+  const bool mirror = sym && tm != tn;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + 16 * i + (lane >> 4) + 4 * r;
+        const int col = n0 + wn + 16 * j + (lane & 15);
+        if (row < q1 && col < q2) {
+          out[(int64_t)row * q2 + col] = acc[i][j][r];
+          if (mirror) out[(int64_t)col * q2 + row] = acc[i][j][r];
+        }
+      }
+}
+
+// Splits of the tiled Gram: about 512 work-groups, a multiple of 8 row
+// ranges (one round per XCD), at least 256 rows each.
+int gram_rt_splits(int64_t n, int ntiles) {
+  int64_t want = (512 + ntiles - 1) / ntiles;
+  want = ((want + 7) / 8) * 8;
+  const int64_t maxs = std::max<int64_t>(1, (n + 255) / 256);
+  return (int)std::max<int64_t>(1, std::min(want, maxs));
+}
+
+bool gram_rt_applies(int q1, int q2) {
+  return std::max(q1, q2) > 128 && q1 <= 256 && q2 <= 256 && !std::getenv("PFEIG_GRAM_OLD");
+}
+
+int gram_rt_tiles(int q1, int q2, bool sym) {
+  const int tm = (q1 + kGramRtTile - 1) / kGramRtTile, tn = (q2 + kGramRtTile - 1) / kGramRtTile;
+  return sym ? tn * (tn + 1) / 2 : tm * tn;
+}
+
 constexpr int kGramSmallMax = 128;
 
 int gram_splits(int64_t n, int q1, int q2) {
@@ -255,6 +372,93 @@ __global__ __launch_bounds__(256) void k_gemm_tall(int64_t n, int q1, int q2,
       }
     }
   }
+}
+
+// Tall GEMM for 128 < max(q1, q2) <= 256: a work-group owns 64 rows of C
+// and every output column; wave w forms columns [64 w, 64 w + 64) of them as
+// 4 x 4 MFMA tiles (64 accumulators per lane), so each element of Bm is read
+// from L2 once per 64 rows (not once per 16-row MFMA tile).  K advances 16 at
+// a time: the 64 x 16 slice of A (k-major) and the 16 x 256 slice of Bm are
+// staged in LDS while the next slices are loaded into registers.  Every A row
+// of the work-group is read before any C row is written, so C may overwrite A.
+constexpr int kGemmRtRows = 64, kGemmRtK = 16, kGemmRtCols = 256;
+
+__global__ __launch_bounds__(256, 2) void k_gemm_rt(int64_t n, int q1, int q2, const double* A,
+                                                 int64_t lda, const double* __restrict__ Bm,
+                                                 double* C, int64_t ldc) {
+  constexpr int RB = kGemmRtRows, KC = kGemmRtK, QC = kGemmRtCols;
+  constexpr int LA = RB * KC / 256, LB = KC * QC / 256;   // 4 and 16 per thread
+  __shared__ double sA[KC][RB + 1];
+  __shared__ double sB[KC][QC + 2];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * RB;
+  const bool active = 64 * wave < q2;   // waves past q2 only help with the loads
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4(0.0);
+  double ra[LA], rb[LB];
+  // A: thread -> (row tid / 4, k (tid % 4) * 4 .. + 3); Bm: idx -> (k idx / 256, column idx % 256)
+  auto fetch = [&](int k0) {
+    const int rr = tid >> 2, kb = (tid & 3) * 4;
+    const int64_t r = r0 + rr;
+#pragma unroll
+    for (int t = 0; t < LA; ++t) {
+      const int k = k0 + kb + t;
+      ra[t] = (r < n && k < q1) ? A[r * lda + k] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < LB; ++t) {
+      const int idx = tid + 256 * t, k = k0 + idx / QC, c = idx % QC;
+      rb[t] = (k < q1 && c < q2) ? Bm[(int64_t)k * q2 + c] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < q1; k0 += KC) {
+    {
+      const int rr = tid >> 2, kb = (tid & 3) * 4;
+#pragma unroll
+      for (int t = 0; t < LA; ++t) sA[kb + t][rr] = ra[t];
+#pragma unroll
+      for (int t = 0; t < LB; ++t) {
+        const int idx = tid + 256 * t;
+        sB[idx / QC][idx % QC] = rb[t];
+      }
+    }
+    __syncthreads();
+    if (k0 + KC < q1) fetch(k0 + KC);
+    if (active) {
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int k = kk + (lane >> 4);
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = sA[k][16 * i + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = sB[k][64 * wave + 16 * j + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(a[i], b[j], acc[i][j]);
+      }
+    }
+    __syncthreads();
+  }
+  if (!active) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + 16 * i + (lane >> 4) + 4 * r;
+      if (row < n) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = 64 * wave + 16 * j + (lane & 15);
+          if (col < q2) C[row * ldc + col] = acc[i][j][r];
+        }
+      }
+    }
 }
 
 // Tall GEMM for q1, q2 <= 128: Bm (padded to KM x 16 NT) is staged once per
@@ -962,12 +1166,33 @@ __global__ void k_scale_by_inv(int64_t n, const double* __restrict__ x,
 
 // ================================================================ launchers
 size_t gram_work_bytes(int64_t n, int q1, int q2) {
-  return (size_t)gram_splits(n, q1, q2) * q1 * q2 * sizeof(double);
+  int ns = gram_splits(n, q1, q2);
+  // the tiled Gram takes at most 256 splits (two or more tiles); callers size
+  // the workspace for their widest product, and a narrower one of the same
+  // call site may use more splits than that product's own count
+  if (std::max(q1, q2) > 128) ns = std::max(ns, 256);
+  return (size_t)ns * q1 * q2 * sizeof(double);
 }
 
 hipError_t gram_f64(int64_t n, int q1, int q2, const double* A, int64_t lda, const double* B,
                     int64_t ldb, double* G, void* work, hipStream_t s) {
   if (q1 == 0 || q2 == 0) return hipSuccess;
+  if (gram_rt_applies(q1, q2)) {
+    const bool sym = A == B && lda == ldb && q1 == q2;
+    const int ntiles = gram_rt_tiles(q1, q2, sym);
+    const int tiles_n = (q2 + kGramRtTile - 1) / kGramRtTile;
+    const int nsplit = gram_rt_splits(n, ntiles);
+    int64_t rows = (n + nsplit - 1) / nsplit;
+    rows = ((rows + kGramRtRows - 1) / kGramRtRows) * kGramRtRows;
+    const int rounds = (nsplit + 7) / 8;
+    double* w = static_cast<double*>(work);
+    hipLaunchKernelGGL(k_gram_rt, dim3((unsigned)(rounds * 8 * ntiles)), dim3(256), 0, s, n, q1,
+                       q2, A, lda, B, ldb, rows, nsplit, tiles_n, ntiles, sym ? 1 : 0, w);
+    const int64_t count = (int64_t)q1 * q2;
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks(count, 16)), dim3(256), 0, s, nsplit, count, w,
+                       G);
+    return hipGetLastError();
+  }
   const int nsplit = gram_splits(n, q1, q2);
   int64_t rows = (n + nsplit - 1) / nsplit;
   rows = ((rows + kGramSmallRows - 1) / kGramSmallRows) * kGramSmallRows;
@@ -1014,6 +1239,11 @@ hipError_t gemm_tall_f64(int64_t n, int q1, int q2, const double* A, int64_t lda
     PFE_GEMM_ROW(1) PFE_GEMM_ROW(2) PFE_GEMM_ROW(3) PFE_GEMM_ROW(4)
 #undef PFE_GEMM_ROW
 #undef PFE_GEMM_CASE
+  }
+  if (q1 <= kGemmRtCols && q2 <= kGemmRtCols && !std::getenv("PFEIG_GEMM_OLD")) {
+    hipLaunchKernelGGL(k_gemm_rt, dim3(nblocks(n, kGemmRtRows)), dim3(256), 0, s, n, q1, q2, A,
+                       lda, Bm, C, ldc);
+    return hipGetLastError();
   }
   const int q1p = ((q1 + 3) / 4) * 4 + 1;
   if ((size_t)32 * q1p * sizeof(double) <= 65536) {

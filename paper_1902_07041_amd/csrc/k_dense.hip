@@ -667,6 +667,8 @@ __device__ __forceinline__ void rr_pair(int m, int step, int k, int* p, int* q) 
   }
 }
 
+constexpr int kJb = 4;   // 2 x 2 blocks per batch in k_jacobi
+
 __global__ __launch_bounds__(1024) void k_jacobi(int q, const double* __restrict__ S,
                                                  double* A, double* V, double* evals, double* Q,
                                                  int* info) {
@@ -696,6 +698,9 @@ __global__ __launch_bounds__(1024) void k_jacobi(int q, const double* __restrict
   int sweep = 0;
   const int max_sweeps = 60;
   bool converged = (q < 2);
+  // threads per row pair in the fused update (a power of two)
+  int tpp = 1;
+  while (tpp * 2 * half <= nt && tpp < 32) tpp *= 2;
   for (; sweep < max_sweeps && !converged; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -721,35 +726,84 @@ __global__ __launch_bounds__(1024) void k_jacobi(int q, const double* __restrict
         qq[tid] = r;
       }
       __syncthreads();
-      // rows p, r of A
-      // rows p, r of A and of V^T (V is kept transposed, so both passes
-      // below touch contiguous rows except A's columns)
-      for (int k = tid >> 5; k < half; k += nt >> 5) {
-        const double s = sn[k];
-        if (s == 0.0) continue;
-        const double c = cs[k];
+      // One pass per step: rows p, r of the pair k meet columns p', r' of
+      // every pair k' in a 2 x 2 block, which takes the row rotation of k and
+      // then the column rotation of k' (the same products, in the same order,
+      // as rotating all rows first and all columns after; a pair without a
+      // rotation changes nothing).  The rotated pair's own off-diagonal
+      // entries get their exact zero.  V is kept transposed: its rows p, r
+      // take the row rotation only.
+      for (int w = tid; w < half * tpp; w += nt) {
+        const int k = w / tpp, sub = w % tpp;
+        const double c = cs[k], s = sn[k];
         const int p = pp[k], r = qq[k];
-        for (int j = tid & 31; j < q; j += 32) {
-          const double a = A[p * q + j], b = A[r * q + j];
-          A[p * q + j] = c * a - s * b;
-          A[r * q + j] = s * a + c * b;
-          const double va = V[p * q + j], vb = V[r * q + j];
-          V[p * q + j] = c * va - s * vb;
-          V[r * q + j] = s * va + c * vb;
+        const bool rp = p < q, rr = r < q;
+        // blocks in batches of kJb: all loads of a batch are issued before
+        // its stores (they touch distinct entries, which the compiler cannot
+        // see through one pointer)
+        for (int k0 = sub; k0 < half; k0 += kJb * tpp) {
+          double a[kJb][4];
+#pragma unroll
+          for (int b = 0; b < kJb; ++b) {
+            const int k2 = k0 + b * tpp;
+            const bool in = k2 < half;
+            const int p2 = in ? pp[k2] : q, r2 = in ? qq[k2] : q;
+            a[b][0] = (rp && p2 < q) ? A[p * q + p2] : 0.0;
+            a[b][1] = (rp && r2 < q) ? A[p * q + r2] : 0.0;
+            a[b][2] = (rr && p2 < q) ? A[r * q + p2] : 0.0;
+            a[b][3] = (rr && r2 < q) ? A[r * q + r2] : 0.0;
+          }
+#pragma unroll
+          for (int b = 0; b < kJb; ++b) {
+            const int k2 = k0 + b * tpp;
+            if (k2 >= half) continue;
+            double a11 = a[b][0], a12 = a[b][1], a21 = a[b][2], a22 = a[b][3];
+            if (s != 0.0) {
+              const double b11 = c * a11 - s * a21, b21 = s * a11 + c * a21;
+              const double b12 = c * a12 - s * a22, b22 = s * a12 + c * a22;
+              a11 = b11;
+              a21 = b21;
+              a12 = b12;
+              a22 = b22;
+            }
+            const double c2 = cs[k2], s2 = sn[k2];
+            if (s2 != 0.0) {
+              const double b11 = c2 * a11 - s2 * a12, b12 = s2 * a11 + c2 * a12;
+              const double b21 = c2 * a21 - s2 * a22, b22 = s2 * a21 + c2 * a22;
+              a11 = b11;
+              a12 = b12;
+              a21 = b21;
+              a22 = b22;
+              if (k2 == k) {
+                a12 = 0.0;
+                a21 = 0.0;
+              }
+            }
+            const int p2 = pp[k2], r2 = qq[k2];
+            if (rp && p2 < q) A[p * q + p2] = a11;
+            if (rp && r2 < q) A[p * q + r2] = a12;
+            if (rr && p2 < q) A[r * q + p2] = a21;
+            if (rr && r2 < q) A[r * q + r2] = a22;
+          }
         }
-      }
-      __syncthreads();
-      // columns p, r of A; the rotated pair's off-diagonal entries are set
-      // to their exact zero here
-      for (int k = tid >> 5; k < half; k += nt >> 5) {
-        const double s = sn[k];
-        if (s == 0.0) continue;
-        const double c = cs[k];
-        const int p = pp[k], r = qq[k];
-        for (int i = tid & 31; i < q; i += 32) {
-          const double a = A[i * q + p], b = A[i * q + r];
-          A[i * q + p] = (i == r) ? 0.0 : c * a - s * b;
-          A[i * q + r] = (i == p) ? 0.0 : s * a + c * b;
+        if (s != 0.0) {
+          for (int j0 = sub; j0 < q; j0 += 2 * kJb * tpp) {
+            double va[2 * kJb], vb[2 * kJb];
+#pragma unroll
+            for (int b = 0; b < 2 * kJb; ++b) {
+              const int j2 = j0 + b * tpp;
+              va[b] = j2 < q ? V[p * q + j2] : 0.0;
+              vb[b] = j2 < q ? V[r * q + j2] : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < 2 * kJb; ++b) {
+              const int j2 = j0 + b * tpp;
+              if (j2 < q) {
+                V[p * q + j2] = c * va[b] - s * vb[b];
+                V[r * q + j2] = s * va[b] + c * vb[b];
+              }
+            }
+          }
         }
       }
       __syncthreads();

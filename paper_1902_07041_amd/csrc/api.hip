@@ -228,11 +228,18 @@ int64_t round_up(int64_t v, int64_t m) { return ((v + m - 1) / m) * m; }
 #define PFE_TILE_ROWS 2
 #endif
 constexpr int kDefaultTileRows = PFE_TILE_ROWS;
-// FP32 filter: three-row tiles keep 8 waves per SIMD (50 VGPRs) and measured
-// 4 % (1e5 atoms) and 8 % (1e6) faster steps at q = 96 than two-row ones,
-// which FP64 keeps (three rows need 92 VGPRs there).  PFEIG_TILE_ROWS_F32
-// overrides.
+// FP32 filter: three-row tiles measured 4 % (1e5 atoms) and 8 % (1e6) faster
+// steps at q = 96 than two-row ones, which FP64 keeps (three rows need 92
+// VGPRs there).  Above kWideF32 columns (one 256-column pass, four floats per
+// lane) four-row tiles share more gathers and win despite fewer waves: 4e6
+// atoms, q = 256: 12.75 against 13.35 ms per step; at q = 160 and below they
+// lose (9.40 against 8.86 ms), and five or six rows lose everywhere.  The
+// height follows the block width of the solve (or of the filter call), so
+// columns locked during a solve never rebuild the tiles.
+// PFEIG_TILE_ROWS_F32 overrides.
 constexpr int kDefaultTileRowsF32 = 3;
+constexpr int kWideTileRowsF32 = 4;
+constexpr int kWideF32 = 192;
 // Locality order of the row tiles: rows per leaf range of the bisection
 // (best of 16..1024 in a per-XCD L2 model); a window of rows of the order of
 // what the 256 MB Infinity Cache holds of T_in at q = 96 in FP64 (2304 B per
@@ -350,8 +357,8 @@ Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double
 }
 
 // FP32 row tiles of height R32 over the FP64 tiles' pattern and order.
-Err ensure_tiles32(pfe_handle h) {
-  int R32 = kDefaultTileRowsF32;
+Err ensure_tiles32(pfe_handle h, int width) {
+  int R32 = width > kWideF32 ? kWideTileRowsF32 : kDefaultTileRowsF32;
   if (const char* v = std::getenv("PFEIG_TILE_ROWS_F32")) R32 = std::atoi(v);
   if (h->tile_rows < 2 || R32 < 2 || R32 > 4 || R32 == h->tile_rows) {
     h->release_tiles32();   // the FP32 filter walks the FP64 tiles
@@ -382,8 +389,10 @@ Err ensure_tiles32(pfe_handle h) {
   return pfe::ok();
 }
 
-Err ensure_h32(pfe_handle h, double c, double e) {
-  PFE_TRY(ensure_tiles32(h));
+// FP32 copy of H_hat in the order of the FP32 tiles for filters `width`
+// columns wide.
+Err ensure_h32(pfe_handle h, double c, double e, int width) {
+  PFE_TRY(ensure_tiles32(h, width));
   const int R32 = h->tile32_rows >= 2 ? h->tile32_rows : h->tile_rows;
   if (h->H32.p && h->h32_c == c && h->h32_e == e && h->h32_R == R32) return pfe::ok();
   const int64_t nel = (h->nnzb + pfe::kBsrPad) * 9;
@@ -1064,7 +1073,7 @@ static Err apply_impl(pfe_handle h, const pfe_filter* f, int nvec, const void* X
                                (const double*)Xd, (double*)Yd, h->wsA.as<double>(), nvec, ld,
                                nullptr));
   } else {
-    PFE_TRY(ensure_h32(h, f->c, f->e));
+    PFE_TRY(ensure_h32(h, f->c, f->e, nvec));
     PFE_TRY(run_filter<float>(h, h->H32.as<float>(), coef, 1.0, 0.0, (const float*)Xd,
                               (float*)Yd, h->wsA.as<float>(), nvec, ld, nullptr));
   }
@@ -1170,7 +1179,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   } else {
     PFE_HIP(pfe::gaussian_fill_f64(n, q, X, ld, o.seed, h->stream));
   }
-  if (mixed) PFE_TRY(ensure_h32(h, fd.c, fd.e));
+  if (mixed) PFE_TRY(ensure_h32(h, fd.c, fd.e, q));
   double bound = 1.05 * coef_abs_sum(fd.coef) + 1e-12;
   int stall = 0;
   const int max_degree = std::min(200000, 8 * std::max(fd.degree, 1));

@@ -354,7 +354,7 @@ def main() -> int:
         "device_bytes_library": P.pfe_device_bytes(h),
         "device_bytes_torch_peak": int(torch.cuda.max_memory_allocated(dev)),
         "orthogonalisation_mfma": {
-            "kernels": "k_gram_partial + k_gram_reduce (Gram), k_gemm_tall (X R^-1, X Q, W Q); FP64 MFMA",
+            "kernels": "k_gram_rt + k_gram_reduce (Gram; 2 n q^2 flops each, the symmetric ones form 3 of 4 tiles), k_gemm_rt (X R^-1, X Q, W Q); FP64 MFMA",
             "flops": s64["gemm_flops"], "seconds": med_stat("o64", "t_gemm"),
             "achieved_TFLOPs": s64["gemm_flops"] / med_stat("o64", "t_gemm") / 1e12,
             "peak_TFLOPs": FP64_MFMA_PEAK_TFLOPS,

@@ -90,16 +90,23 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
+# the FP64 filter's kernel at the benchmark shape: three-row tiles (one record
+# per batch) of the wide-block tile set, two 128-column passes per launch
+K64_INSTANCE = "k_cheb_tile<double, 2, 1, 1, 3>"
+
+
 def traffic_from_profile():
     """HBM bytes per FP64 filter launch at the benchmark shape from the
     committed rocprofv3 counter summary, if it was taken on the current
-    kernel source."""
+    kernel source and kernel instance."""
     p = os.path.join(ROOT, "profiles", "k1_fp64_q256_glass4m_traffic.json")
     try:
         d = json.load(open(p))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if d.get("kernel_instance") != K64_INSTANCE:
         return None
     return d.get("bytes_per_launch")
 
@@ -303,8 +310,8 @@ def main() -> int:
     def med_stat(form, key):
         return float(np.median([r[form]["stats"][key] for r in res]))
 
-    # dominant kernel: the fused FP64 Clenshaw step (k_cheb_tile<double, 2, 1, 2, 2>,
-    # two 128-column passes per launch at q = 256), in the FP64 iteration's
+    # dominant kernel: the fused FP64 Clenshaw step (K64_INSTANCE, two
+    # 128-column passes per launch at q = 256), in the FP64 iteration's
     # filter: its launches are timed by the library with HIP events on this
     # stream.  Algorithmic bytes per launch as in the method's fused step
     # (Algorithm 2 with a running sum): matrix values, column indices and
@@ -379,8 +386,8 @@ def main() -> int:
                            "adjoint": "ceil(sqrt(150)) = 13-step checkpoint segments, recomputed"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(),
-                     "kernel": "k_cheb_tile<double,2,1,2,2> (fused BSR3 Clenshaw step, two-row "
-                               "tiles, two 128-column passes), the FP64 iteration's 300 launches",
+                     "kernel": K64_INSTANCE + " (fused BSR3 Clenshaw step, three-row tiles, "
+                               "two 128-column passes), the FP64 iteration's 300 launches",
                      "avg_launch_us": 1e6 * launch64,
                      "algorithmic_bytes_per_launch": bstep,
                      "clenshaw_stream_bytes_per_launch": clen,

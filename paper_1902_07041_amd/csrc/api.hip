@@ -84,6 +84,13 @@ struct pfe_ctx {
   int64_t n_tiles32 = 0;
   DevBuf t32_ptr, t32_vptr, t32_cm, t32_row, t32_perm;
   int h32_R = 0;              // tile height H32's order was made for
+  // Row tiles of the FP64 filter for wide blocks (same pattern and order,
+  // more rows per tile) and the block values in their order (refreshed after
+  // every new value set, at the next wide filter).
+  int tile64w_rows = 0;
+  int64_t n_tiles64w = 0;
+  DevBuf w64_ptr, w64_vptr, w64_cm, w64_row, w64_perm, Hw;
+  bool hw_valid = false;
   // bounds
   bool has_bounds = false;
   double lam_lb = 0, lam_ub = 0;
@@ -125,6 +132,27 @@ struct pfe_ctx {
       a.tile_row = t32_row.as<int32_t>();
     }
     return a;
+  }
+  pfe::Bsr bsr64w() const {
+    pfe::Bsr a = bsr();
+    a.tile_rows = tile64w_rows;
+    a.n_tiles = n_tiles64w;
+    a.tile_ptr = w64_ptr.as<int64_t>();
+    a.tile_vptr = w64_vptr.as<int64_t>();
+    a.tile_cm = w64_cm.as<int2>();
+    a.tile_row = w64_row.as<int32_t>();
+    return a;
+  }
+  void release_tiles64w() {
+    tile64w_rows = 0;
+    n_tiles64w = 0;
+    hw_valid = false;
+    w64_ptr.release();
+    w64_vptr.release();
+    w64_cm.release();
+    w64_row.release();
+    w64_perm.release();
+    Hw.release();
   }
   void release_tiles32() {
     tile32_rows = 0;
@@ -240,6 +268,13 @@ constexpr int kDefaultTileRows = PFE_TILE_ROWS;
 constexpr int kDefaultTileRowsF32 = 3;
 constexpr int kWideTileRowsF32 = 4;
 constexpr int kWideF32 = 192;
+// FP64 filter above kWideF64 columns (two 128-column passes): three-row tiles
+// (one record per batch) measured 5 % faster steps on the 4e6-atom glass at
+// q = 256 and slower ones at q = 160 (passes of 80) and q = 96; they get a
+// tile set and a copy of the block values of their own, used by the wide
+// filters only.  PFEIG_TILE_ROWS_F64W overrides (0: none).
+constexpr int kWideTileRowsF64 = 3;
+constexpr int kWideF64 = 192;
 // Locality order of the row tiles: rows per leaf range of the bisection
 // (best of 16..1024 in a per-XCD L2 model); a window of rows of the order of
 // what the 256 MB Infinity Cache holds of T_in at q = 96 in FP64 (2304 B per
@@ -305,8 +340,9 @@ struct Timer {
 // d launches for d >= 1.
 template <typename T>
 Err run_filter(pfe_handle h, const T* vals, const double* g, int d, double a1, double b1,
-               const T* X, T* P, T* Q, int q, int64_t ld, int64_t* steps) {
-  const pfe::Bsr A = sizeof(T) == 4 ? h->bsr32() : h->bsr();
+               const T* X, T* P, T* Q, int q, int64_t ld, int64_t* steps,
+               const pfe::Bsr* over = nullptr) {
+  const pfe::Bsr A = over ? *over : (sizeof(T) == 4 ? h->bsr32() : h->bsr());
   auto step = [&](const T* tin, const T* prev, T* out, double al, double be, double de,
                   double ze) -> hipError_t {
     if constexpr (sizeof(T) == 8)
@@ -352,8 +388,55 @@ Err run_filter(pfe_handle h, const T* vals, const double* g, int d, double a1, d
 
 template <typename T>
 Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double a1, double b1,
-               const T* X, T* P, T* Q, int q, int64_t ld, int64_t* steps) {
-  return run_filter<T>(h, vals, g.data(), (int)g.size() - 1, a1, b1, X, P, Q, q, ld, steps);
+               const T* X, T* P, T* Q, int q, int64_t ld, int64_t* steps,
+               const pfe::Bsr* over = nullptr) {
+  return run_filter<T>(h, vals, g.data(), (int)g.size() - 1, a1, b1, X, P, Q, q, ld, steps, over);
+}
+
+// The pattern and block values an FP64 filter on blocks `width` columns wide
+// walks: the wide tile set above kWideF64 (built at its first use, values
+// re-permuted after every new value set), else the handle's own tiles.
+Err filter_set64(pfe_handle h, int width, pfe::Bsr* A, const double** vals) {
+  *A = h->bsr();
+  *vals = h->step_vals64();
+  int Rw = width > kWideF64 ? kWideTileRowsF64 : 0;
+  if (const char* v = std::getenv("PFEIG_TILE_ROWS_F64W")) Rw = std::atoi(v);
+  if (h->tile_rows < 2 || Rw < 2 || Rw > 4 || Rw == h->tile_rows) return pfe::ok();
+  if (h->tile64w_rows != Rw) {
+    h->release_tiles64w();
+    const int64_t na = h->n_atoms;
+    std::vector<int32_t> order;
+    if (h->tiled_local)
+      pfe::locality_order(na, h->tiled_rp.data(), h->tiled_ci.data(), kOrderLeaf, Rw, order);
+    std::vector<int64_t> tp, tv, perm;
+    std::vector<int32_t> tcm, trow;
+    pfe::build_row_tiles(na, h->tiled_rp.data(), h->tiled_ci.data(), Rw,
+                         h->tiled_local ? order.data() : nullptr, tp, tv, tcm, trow, perm);
+    PFE_HIP(h->w64_ptr.ensure(tp.size() * sizeof(int64_t)));
+    PFE_HIP(h->w64_vptr.ensure(tv.size() * sizeof(int64_t)));
+    PFE_HIP(h->w64_cm.ensure(tcm.size() * sizeof(int32_t)));
+    PFE_HIP(h->w64_row.ensure(trow.size() * sizeof(int32_t)));
+    PFE_HIP(h->w64_perm.ensure(perm.size() * sizeof(int64_t)));
+    PFE_HIP(hipMemcpy(h->w64_ptr.p, tp.data(), tp.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    PFE_HIP(hipMemcpy(h->w64_vptr.p, tv.data(), tv.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    PFE_HIP(hipMemcpy(h->w64_cm.p, tcm.data(), tcm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    PFE_HIP(hipMemcpy(h->w64_row.p, trow.data(), trow.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    PFE_HIP(hipMemcpy(h->w64_perm.p, perm.data(), perm.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    h->n_tiles64w = (int64_t)tp.size() - 1;
+    h->tile64w_rows = Rw;
+    h->hw_valid = false;
+  }
+  if (!h->hw_valid) {
+    const int64_t nel = (h->nnzb + pfe::kBsrPad) * 9;
+    PFE_HIP(h->Hw.ensure((size_t)nel * sizeof(double)));
+    PFE_HIP(pfe::zero_f64(h->Hw.as<double>(), nel, h->stream));
+    PFE_HIP(pfe::permute_blocks_f64(h->nnzb, h->w64_perm.as<int64_t>(), h->H.as<double>(),
+                                    h->Hw.as<double>(), h->stream));
+    h->hw_valid = true;
+  }
+  *A = h->bsr64w();
+  *vals = h->Hw.as<double>();
+  return pfe::ok();
 }
 
 // FP32 row tiles of height R32 over the FP64 tiles' pattern and order.
@@ -669,7 +752,8 @@ int64_t pfe_device_bytes(pfe_handle h) {
                           &h->row_ptr, &h->col_idx, &h->H,    &h->transpose, &h->masses,
                           &h->H32,     &h->flags,   &h->wsA,  &h->wsB,       &h->wsC,
                           &h->wsD,     &h->wsSmall, &h->wsRed, &h->wsOut,    &h->wsCk, &h->wsSlice,
-                          &h->t32_ptr, &h->t32_vptr, &h->t32_cm, &h->t32_row, &h->t32_perm};
+                          &h->t32_ptr, &h->t32_vptr, &h->t32_cm, &h->t32_row, &h->t32_perm,
+                          &h->w64_ptr, &h->w64_vptr, &h->w64_cm, &h->w64_row, &h->w64_perm, &h->Hw};
   int64_t s = 0;
   for (auto* b : bufs) s += (int64_t)b->bytes;
   return s;
@@ -770,6 +854,7 @@ static Err set_hessian_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const i
       h->n_tiles = 0;
       h->tiled_R = 0;
       h->release_tiles32();
+      h->release_tiles64w();
       std::vector<int64_t> tp, tv, perm;
       std::vector<int32_t> tcm, trow, order;
       // Rows whose neighbours lie far away in the given numbering (an MD
@@ -814,6 +899,7 @@ static Err set_hessian_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const i
     PFE_HIP(pfe::permute_blocks_f64(nnzb, h->tile_perm.as<int64_t>(), h->H.as<double>(),
                                     h->Ht.as<double>(), h->stream));
     h->tile_rows = R;
+    h->hw_valid = false;   // the wide tiles' values follow at their next use
   } else {
     h->tile_rows = 0;
     h->n_tiles = 0;
@@ -827,6 +913,7 @@ static Err set_hessian_impl(pfe_handle h, int64_t n_atoms, int64_t nnzb, const i
     h->tile_perm.release();
     h->Ht.release();
     h->release_tiles32();
+    h->release_tiles64w();
   }
   PFE_TRY(sync(h));
   h->has_h = true;
@@ -1069,9 +1156,11 @@ static Err apply_impl(pfe_handle h, const pfe_filter* f, int nvec, const void* X
     Yd = h->wsD.p;
   }
   if (precision == PFE_FP64) {
-    PFE_TRY(run_filter<double>(h, h->step_vals64(), coef, 1.0 / f->e, -f->c / f->e,
-                               (const double*)Xd, (double*)Yd, h->wsA.as<double>(), nvec, ld,
-                               nullptr));
+    pfe::Bsr A64;
+    const double* v64 = nullptr;
+    PFE_TRY(filter_set64(h, nvec, &A64, &v64));
+    PFE_TRY(run_filter<double>(h, v64, coef, 1.0 / f->e, -f->c / f->e, (const double*)Xd,
+                               (double*)Yd, h->wsA.as<double>(), nvec, ld, nullptr, &A64));
   } else {
     PFE_TRY(ensure_h32(h, f->c, f->e, nvec));
     PFE_TRY(run_filter<float>(h, h->H32.as<float>(), coef, 1.0, 0.0, (const float*)Xd,
@@ -1254,9 +1343,12 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
           std::swap(Fin, Fout);
           st.filter_columns += nf;
         }
+        pfe::Bsr A64;
+        const double* v64 = nullptr;
+        PFE_TRY(filter_set64(h, q, &A64, &v64));
         Timer tm(h, &st.t_filter);
-        PFE_TRY(run_filter<double>(h, h->step_vals64(), fd.coef, 1.0 / fd.e, -fd.c / fd.e, Fin,
-                                   Fout, (double*)R, nf, ld, &st.filter_steps));
+        PFE_TRY(run_filter<double>(h, v64, fd.coef, 1.0 / fd.e, -fd.c / fd.e, Fin, Fout,
+                                   (double*)R, nf, ld, &st.filter_steps, &A64));
         st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 8, fd.degree);
         if (mixed) st.refine_applications++;
       }

@@ -390,3 +390,38 @@ def test_new_pattern_on_a_handle_rebuilds_both_tile_sets(case):
             assert rel_err(P.pfe_apply_filter(h, f, X), ref) < 1e-12
     finally:
         P.pfe_destroy(h)
+
+
+def test_wide_tile_sets_on_one_handle(case, monkeypatch):
+    """Blocks wider than 192 columns walk tile sets of their own: four-row
+    tiles in FP32 and three-row tiles with a copy of the block values in FP64
+    (two-row tiles below).  Every height gives the same bits, a new value set
+    on the same pattern refreshes the wide copy, and both match the oracle."""
+    banner("apply_filter at q=256: wide tile sets vs the handle's own")
+    for v in ("PFEIG_TILE_ROWS", "PFEIG_TILE_ROWS_F32", "PFEIG_TILE_ROWS_F64W"):
+        monkeypatch.delenv(v, raising=False)
+    g = case.g
+    f = design(case, 20)
+    X = gaussian_block(case.n, 256, 71)
+    h = P.pfe_create(0)
+    try:
+        for scale in (1.0, 1.5):   # the second value set: H scaled, same pattern
+            P.pfe_set_hessian(h, g.row_ptr, g.col_idx, g.blocks * scale, g.masses)
+            P.pfe_set_bounds(h, 0.0, case.ub * scale)
+            fs = P.pfe_design_filter(0.01 * case.lam[-1] * scale, 0.03 * case.lam[-1] * scale,
+                                     0.0, case.ub * scale, degree=20)
+            ref = chebyshev.apply_filter(case.H * scale, fs.c, fs.e, fs.coef, X)
+            wide64 = P.pfe_apply_filter(h, fs, X)
+            wide32 = P.pfe_apply_filter(h, fs, X.astype(np.float32))
+            monkeypatch.setenv("PFEIG_TILE_ROWS_F64W", "0")
+            monkeypatch.setenv("PFEIG_TILE_ROWS_F32", "3")
+            own64 = P.pfe_apply_filter(h, fs, X)
+            own32 = P.pfe_apply_filter(h, fs, X.astype(np.float32))
+            monkeypatch.delenv("PFEIG_TILE_ROWS_F64W")
+            monkeypatch.delenv("PFEIG_TILE_ROWS_F32")
+            np.testing.assert_array_equal(wide64, own64)
+            np.testing.assert_array_equal(wide32, own32)
+            assert rel_err(wide64, ref) < 1e-12
+            assert rel_err(wide32, ref) < 5e-5
+    finally:
+        P.pfe_destroy(h)

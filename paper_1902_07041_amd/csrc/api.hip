@@ -1289,7 +1289,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   const int max_sweeps = o.refine_sweeps > 0 ? o.refine_sweeps : 1;
   int refine_m = 1;         // filter applications of the current refinement sweep
   double refine_kap = 0.0;  // contraction per application it was sized for
-  double prev2_max = HUGE_VAL;
+  double good_ratio = 0.0;  // the FP32 phase's last contraction below 0.5 per iteration
   for (int it = 1; it <= o.max_iter; ++it) {
     // Locking: the Ritz vectors of the last Rayleigh-Ritz step that lie in the
     // window with residual <= tol are not filtered.  The others (rounded up
@@ -1351,6 +1351,11 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
                                    (double*)R, nf, ld, &st.filter_steps, &A64));
         st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 8, fd.degree);
         if (mixed) st.refine_applications++;
+        if (trace && reps > 1) {
+          PFE_TRY(sync(h));
+          std::fprintf(stderr, "[pfeig]   FP64 application %d of %d done t=%.3fs\n", rep + 1, reps,
+                       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        }
       }
       st.fp64_iterations++;
     } else {
@@ -1437,7 +1442,6 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       if (trace) std::fprintf(stderr, "[pfeig] refinement sweep %d: %d FP64 filter applications\n",
                               st.refined, refine_m);
       prev_cnt = cnt;
-      prev2_max = prev_max;
       prev_max = mx;
       continue;
     }
@@ -1468,12 +1472,21 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       stall = 0;
       if (trace) std::fprintf(stderr, "[pfeig] plateau: degree raised to %d (eps %.3e)\n", fd.degree, fd.eps);
     }
-    if (!fp64_phase && it >= 2 && cnt == prev_cnt &&
-        ((mx > 0.5 * prev_max && mx <= kFp32Floor) || mx <= 30.0 * o.tol)) {
+    const bool have_prev = prev_max > 0 && std::isfinite(prev_max);
+    if (!fp64_phase && have_prev && mx > 0 && mx < 0.5 * prev_max) good_ratio = mx / prev_max;
+    if (!fp64_phase && it >= 2 && std::abs(cnt - prev_cnt) <= std::max(2, cnt / 50) &&
+        ((have_prev && mx > 0.5 * prev_max && mx <= kFp32Floor) || mx <= 30.0 * o.tol)) {
       // FP32 iterations have stalled at their rounding level (or are within
-      // reach of tol): the FP64 refinement sweep from here.  Its rate is the
-      // larger of the Ritz values' bound and the last contraction the FP32
-      // iterations showed before the plateau (the bound can come out low
+      // reach of tol): the FP64 refinement sweep from here.  The in-window
+      // count need not have settled: on a large instance the FP32 plateau can
+      // leave Ritz values off by about the window's width (4e6 atoms,
+      // q = 256: residuals of 1.3e-4 of lam_ub against a window 1.4e-4 of it
+      // wide), so the count may still drift by a few (at most 2 % of it)
+      // until the sweep, after which the stop test takes it as it is.  The
+      // sweep's rate is the larger of the Ritz values' bound and the last
+      // contraction the FP32
+      // iterations showed before the plateau, i.e. the last one below 0.5
+      // (the plateau's own ratios are near 1; the bound can come out low
       // when the block holds many more vectors than the window, whose Ritz
       // values are poor).  The plateau is FP32 rounding spread over every
       // eigendirection, most of which the first FP64 application removes;
@@ -1481,14 +1494,12 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       // residual times that rate.
       fp64_phase = true;
       st.refined = 1;
-      const double seen = (prev2_max > 0 && std::isfinite(prev2_max)) ? prev_max / prev2_max : 0.0;
-      refine_kap = std::max(rate_bound(), seen);
+      refine_kap = std::max(rate_bound(), good_ratio);
       refine_m = sweep_apps(std::min(mx, refine_kap * prev_max), refine_kap);
       if (trace) std::fprintf(stderr, "[pfeig] refinement sweep 1: %d FP64 filter applications\n",
                               refine_m);
     }
     prev_cnt = cnt;
-    prev2_max = prev_max;
     prev_max = mx;
   }
   st.gemm_flops = ga.flops;

@@ -5,8 +5,6 @@
 // counter-based Gaussian generator and small Lanczos helpers.  All
 // reductions are two-pass and in a fixed order (no floating-point atomics),
 // so repeated runs are bitwise identical.
-#include <cstdlib>
-
 #include "internal.h"
 
 namespace pfe {
@@ -296,7 +294,7 @@ int gram_rt_splits(int64_t n, int ntiles) {
 }
 
 bool gram_rt_applies(int q1, int q2) {
-  return std::max(q1, q2) > 128 && q1 <= 256 && q2 <= 256 && !std::getenv("PFEIG_GRAM_OLD");
+  return std::max(q1, q2) > 128 && q1 <= 256 && q2 <= 256;
 }
 
 int gram_rt_tiles(int q1, int q2, bool sym) {
@@ -1294,7 +1292,7 @@ hipError_t gemm_tall_f64(int64_t n, int q1, int q2, const double* A, int64_t lda
 #undef PFE_GEMM_ROW
 #undef PFE_GEMM_CASE
   }
-  if (q1 <= kGemmRtCols && q2 <= kGemmRtCols && !std::getenv("PFEIG_GEMM_OLD")) {
+  if (q1 <= kGemmRtCols && q2 <= kGemmRtCols) {
     hipLaunchKernelGGL(k_gemm_rt, dim3(nblocks(n, kGemmRtRows)), dim3(256), 0, s, n, q1, q2, A,
                        lda, Bm, C, ldc);
     return hipGetLastError();

@@ -515,7 +515,7 @@ struct Small {
   double* Rinv;    // 2 q*q
   double* S;       // q*q
   double* Q;       // q*q
-  double* jw;      // 2 q*q
+  double* jw;      // jacobi_work_bytes(q)
   double* theta;   // q
   double* res;     // q
   double* dmax;    // 4
@@ -525,7 +525,8 @@ struct Small {
 
 Err alloc_small(pfe_handle h, int q, Small* s) {
   const size_t qq = (size_t)q * q;
-  const size_t doubles = qq * 7 + 2 * (size_t)q + 4;
+  const size_t jwd = (pfe::jacobi_work_bytes(q) + sizeof(double) - 1) / sizeof(double);
+  const size_t doubles = qq * 5 + jwd + 2 * (size_t)q + 4;
   const size_t bytes = doubles * sizeof(double) + 8 * sizeof(int) + (size_t)q * sizeof(int) + 256;
   PFE_HIP(h->wsSmall.ensure(bytes));
   double* p = h->wsSmall.as<double>();
@@ -534,7 +535,7 @@ Err alloc_small(pfe_handle h, int q, Small* s) {
   s->S = s->Rinv + 2 * qq;
   s->Q = s->S + qq;
   s->jw = s->Q + qq;
-  s->theta = s->jw + 2 * qq;
+  s->theta = s->jw + jwd;
   s->res = s->theta + q;
   s->dmax = s->res + q;
   s->info = reinterpret_cast<int*>(s->dmax + 4);

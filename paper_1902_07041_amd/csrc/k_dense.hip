@@ -5,6 +5,8 @@
 // counter-based Gaussian generator and small Lanczos helpers.  All
 // reductions are two-pass and in a fixed order (no floating-point atomics),
 // so repeated runs are bitwise identical.
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace pfe {
@@ -823,6 +825,128 @@ __global__ __launch_bounds__(1024) void k_jacobi(int q, const double* __restrict
   if (tid == 0) info[0] = converged ? sweep : -sweep;
 }
 
+// The same Jacobi over several work-groups, one kernel per round-robin step
+// (q above kJacobiOneGroupMax, where one work-group's path to L2 limits the
+// single-kernel form).  A is double-buffered: every work-group forms all of
+// the step's rotations from the previous step's matrix (which no work-group
+// of this step writes), then work-group k applies them to row pair k (its
+// 2 x 2 blocks with every column pair, into the other buffer, then its rows
+// of V^T in place), with the products of k_jacobi; the host reads one flag
+// per sweep.  Work: A0, A1, V [q][q], floor, one flag per sweep.
+constexpr int kJacobiOneGroupMax = 128;
+constexpr int kJacobiMaxSweeps = 60;
+
+__global__ __launch_bounds__(1024) void k_jac_init(int q, const double* __restrict__ S, double* A,
+                                                   double* V, double* floor_abs, int* flags) {
+  __shared__ double red[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double loc = 0.0;
+  for (int idx = tid; idx < q * q; idx += nt) {
+    const int i = idx / q, j = idx % q;
+    const double a = 0.5 * (S[i * q + j] + S[j * q + i]);
+    A[idx] = a;
+    V[idx] = (i == j) ? 1.0 : 0.0;
+    loc += a * a;
+  }
+  red[tid] = loc;
+  if (tid < kJacobiMaxSweeps) flags[tid] = 0;
+  __syncthreads();
+  for (int s = nt / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) floor_abs[0] = 1e-18 * sqrt(red[0]) + 1e-300;
+}
+
+__global__ __launch_bounds__(512) void k_jac_step(int q, int step, const double* __restrict__ Ain,
+                                                  double* __restrict__ Aout, double* V,
+                                                  const double* __restrict__ floor_abs,
+                                                  int* rotated) {
+  __shared__ double cs[512], sn[512];
+  __shared__ int pp[512], qq[512];
+  const int m = q + (q & 1), half = m / 2;
+  const double eps = 2.220446049250313e-16;
+  for (int k = threadIdx.x; k < half; k += blockDim.x) {
+    int p, r;
+    rr_pair(m, step, k, &p, &r);
+    double c = 1.0, s = 0.0;
+    if (p < q && r < q) {
+      const double apq = Ain[p * q + r];
+      const double app = Ain[p * q + p], arr = Ain[r * q + r];
+      if (fabs(apq) > floor_abs[0] && fabs(apq) > eps * sqrt(fabs(app * arr))) {
+        const double theta = (arr - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        c = 1.0 / sqrt(t * t + 1.0);
+        s = t * c;
+        if (blockIdx.x == 0) rotated[0] = 1;
+      }
+    }
+    cs[k] = c;
+    sn[k] = s;
+    pp[k] = p;
+    qq[k] = r;
+  }
+  __syncthreads();
+  const int k = blockIdx.x;
+  const double c = cs[k], s = sn[k];
+  const int p = pp[k], r = qq[k];
+  const bool rp = p < q, rr = r < q;
+  for (int k2 = threadIdx.x; k2 < half; k2 += blockDim.x) {
+    const double c2 = cs[k2], s2 = sn[k2];
+    const int p2 = pp[k2], r2 = qq[k2];
+    const bool cp = p2 < q, cr = r2 < q;
+    double a11 = (rp && cp) ? Ain[p * q + p2] : 0.0, a12 = (rp && cr) ? Ain[p * q + r2] : 0.0;
+    double a21 = (rr && cp) ? Ain[r * q + p2] : 0.0, a22 = (rr && cr) ? Ain[r * q + r2] : 0.0;
+    if (s != 0.0) {
+      const double b11 = c * a11 - s * a21, b21 = s * a11 + c * a21;
+      const double b12 = c * a12 - s * a22, b22 = s * a12 + c * a22;
+      a11 = b11;
+      a21 = b21;
+      a12 = b12;
+      a22 = b22;
+    }
+    if (s2 != 0.0) {
+      const double b11 = c2 * a11 - s2 * a12, b12 = s2 * a11 + c2 * a12;
+      const double b21 = c2 * a21 - s2 * a22, b22 = s2 * a21 + c2 * a22;
+      a11 = b11;
+      a12 = b12;
+      a21 = b21;
+      a22 = b22;
+      if (k2 == k) {
+        a12 = 0.0;
+        a21 = 0.0;
+      }
+    }
+    if (rp && cp) Aout[p * q + p2] = a11;
+    if (rp && cr) Aout[p * q + r2] = a12;
+    if (rr && cp) Aout[r * q + p2] = a21;
+    if (rr && cr) Aout[r * q + r2] = a22;
+  }
+  if (s != 0.0) {
+    for (int j = threadIdx.x; j < q; j += blockDim.x) {
+      const double va = V[p * q + j], vb = V[r * q + j];
+      V[p * q + j] = c * va - s * vb;
+      V[r * q + j] = s * va + c * vb;
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_jac_final(int q, const double* __restrict__ A,
+                                                    const double* __restrict__ V, double* evals,
+                                                    double* Q, int* info, int sweeps) {
+  for (int i = threadIdx.x; i < q; i += blockDim.x) {
+    const double di = A[i * q + i];
+    int rank = 0;
+    for (int j = 0; j < q; ++j) {
+      const double dj = A[j * q + j];
+      if (dj < di || (dj == di && j < i)) ++rank;
+    }
+    evals[rank] = di;
+    for (int r = 0; r < q; ++r) Q[r * q + rank] = V[i * q + r];   // V holds V^T
+  }
+  if (threadIdx.x == 0) info[0] = sweeps;
+}
+
 // LDS-resident variant for q <= kJacobiLdsMax: A and V^T live in LDS with
 // row stride q+1 (column sweeps hit distinct banks); same ordering, skip
 // rule and stopping rule as k_jacobi.
@@ -1324,7 +1448,9 @@ hipError_t chol_inv_f64(int q, const double* G, double shift, double* Rinv, int*
   return hipGetLastError();
 }
 
-size_t jacobi_work_bytes(int q) { return (size_t)2 * q * q * sizeof(double); }
+size_t jacobi_work_bytes(int q) {
+  return ((size_t)3 * q * q + 16) * sizeof(double) + kJacobiMaxSweeps * sizeof(int);
+}
 
 hipError_t sym_eig_f64(int q, const double* S, double* evals, double* Q, void* work, int* info,
                        hipStream_t s) {
@@ -1335,7 +1461,38 @@ hipError_t sym_eig_f64(int q, const double* S, double* evals, double* Q, void* w
   }
   double* A = static_cast<double*>(work);
   double* V = A + (int64_t)q * q;
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, q, S, A, V, evals, Q, info);
+  if (q <= kJacobiOneGroupMax || std::getenv("PFEIG_JACOBI_ONE_GROUP")) {
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, q, S, A, V, evals, Q, info);
+    return hipGetLastError();
+  }
+  const int m = q + (q & 1), half = m / 2;
+  double* A1 = V + (int64_t)q * q;
+  double* floor_abs = A1 + (int64_t)q * q;
+  int* flags = reinterpret_cast<int*>(floor_abs + 2);
+  hipLaunchKernelGGL(k_jac_init, dim3(1), dim3(1024), 0, s, q, S, A, V, floor_abs, flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned bt = (unsigned)std::min(512, ((half + 63) / 64) * 64);
+  double* Ab[2] = {A, A1};
+  int cur = 0;
+  int sweep = 0;
+  bool converged = false;
+  for (; sweep < kJacobiMaxSweeps && !converged; ++sweep) {
+    for (int step = 0; step < m - 1; ++step) {
+      hipLaunchKernelGGL(k_jac_step, dim3((unsigned)half), dim3(bt), 0, s, q, step, Ab[cur],
+                         Ab[cur ^ 1], V, floor_abs, flags + sweep);
+      cur ^= 1;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int rot = 0;
+    if ((e = hipMemcpyAsync(&rot, flags + sweep, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    converged = rot == 0;
+  }
+  A = Ab[cur];
+  hipLaunchKernelGGL(k_jac_final, dim3(1), dim3(1024), 0, s, q, A, V, evals, Q, info,
+                     converged ? sweep : -sweep);
   return hipGetLastError();
 }
 

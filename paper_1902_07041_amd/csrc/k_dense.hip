@@ -5,8 +5,6 @@
 // counter-based Gaussian generator and small Lanczos helpers.  All
 // reductions are two-pass and in a fixed order (no floating-point atomics),
 // so repeated runs are bitwise identical.
-#include <cstdlib>
-
 #include "internal.h"
 
 namespace pfe {
@@ -1461,7 +1459,7 @@ hipError_t sym_eig_f64(int q, const double* S, double* evals, double* Q, void* w
   }
   double* A = static_cast<double*>(work);
   double* V = A + (int64_t)q * q;
-  if (q <= kJacobiOneGroupMax || std::getenv("PFEIG_JACOBI_ONE_GROUP")) {
+  if (q <= kJacobiOneGroupMax) {
     hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, q, S, A, V, evals, Q, info);
     return hipGetLastError();
   }

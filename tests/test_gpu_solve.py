@@ -238,12 +238,15 @@ def wide():
     P.pfe_destroy(c.h)
 
 
-@pytest.mark.parametrize("q", [160, 256])
+@pytest.mark.parametrize("q", [160, 161, 256])
 def test_solve_wide_blocks_match_dense(wide, q):
     """Blocks above 128 columns take the wide forms of every solver kernel:
-    the partial Gram products, the global-memory Cholesky inverse, the
-    global Jacobi eigensolver and the tall GEMM, all inside the subspace
-    iteration.  The window holds about 0.6 q eigenvalues, its ends in gaps."""
+    the tiled Gram products, the global-memory Cholesky inverse, the Jacobi
+    eigensolver over many work-groups (an odd q pairs one index with a
+    padding index in every round-robin step) and the row-block tall GEMM, all
+    inside the subspace iteration; q = 256 also walks the wide-block tile
+    sets of both filters.  The window holds about 0.6 q eigenvalues, its
+    ends in gaps."""
     lam = wide.lam
     i0 = _gap_index(lam, int(np.searchsorted(lam, 0.02 * lam[-1])))
     i1 = _gap_index(lam, i0 + int(0.6 * q))

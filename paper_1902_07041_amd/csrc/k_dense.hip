@@ -574,19 +574,26 @@ __global__ __launch_bounds__(1024) void k_chol_inv(int q, const double* __restri
     if (tid == 0) info[0] = bad;
     return;
   }
-  // Z = R^{-1} (upper): column j by back substitution
-  for (int j = tid; j < q; j += nt) {
-    for (int i = q - 1; i >= 0; --i) {
-      if (i > j) {
-        Z[i * q + j] = 0.0;
-        continue;
-      }
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int k = i + 1; k <= j; ++k) s -= R[i * q + k] * Z[k * q + j];
-      Z[i * q + j] = s / R[i * q + i];
-    }
-  }
+  // Z = R^{-1} (upper) column by column from Z R = I: column j needs only
+  // the columns before it, and its entries above the diagonal,
+  //   Z[i][j] = -(sum_{i <= k < j} Z[i][k] R[k][j]) / R[j][j],
+  // are independent dot products, four threads each (a group of four lanes
+  // shares its row, so the shuffles stay inside active groups)
+  for (int idx = tid; idx < q * q; idx += nt) Z[idx] = 0.0;
   __syncthreads();
+  for (int j = 0; j < q; ++j) {
+    const double rjj = R[j * q + j];
+    const int sub = tid & 3;
+    for (int i = tid >> 2; i < j; i += nt >> 2) {
+      double acc = 0.0;
+      for (int k = i + sub; k < j; k += 4) acc += Z[i * q + k] * R[k * q + j];
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (sub == 0) Z[i * q + j] = -acc / rjj;
+    }
+    if (tid == 0) Z[j * q + j] = 1.0 / rjj;
+    __syncthreads();
+  }
   for (int idx = tid; idx < q * q; idx += nt) R[idx] = Z[idx];
   if (tid == 0) info[0] = 0;
 }

@@ -41,8 +41,12 @@ def check(H, lam, U, ub, lo, hi, out, ev_tol=1e-10):
 
 @pytest.mark.parametrize("block,basis,smoothing", [(8, 48, P.PFE_SMOOTH_NONE),
                                                    (16, 64, P.PFE_SMOOTH_LANCZOS),
-                                                   (4, 40, P.PFE_SMOOTH_JACKSON)])
+                                                   (4, 40, P.PFE_SMOOTH_JACKSON),
+                                                   (24, 408, P.PFE_SMOOTH_NONE)])
 def test_lanczos_matches_dense(case, block, basis, smoothing):
+    """Against dense LAPACK for three block sizes and dampings; the basis of
+    408 columns (plus a residual block of 24) takes the projected matrix's
+    eigensolve over many work-groups."""
     banner(f"TR-Lanczos N=1000 b={block} m={basis} smoothing={smoothing}")
     out = P.pfe_solve_lanczos(case.h, case.lo, case.hi, 40, block=block, max_basis=basis,
                               smoothing=smoothing, tol=1e-10)

@@ -154,6 +154,58 @@ def cpu_baseline(g, bounds, degree):
     }
 
 
+def solver_variants(P, h, lo, hi, th, X0, ev64, D, W):
+    """One timed run each of the solver variants beyond the benchmark step on
+    the 1e5-atom instance: the FP64 solve without locking, the stochastic
+    count, thick-restart block Lanczos on the Dirac filter, and spectrum
+    slicing of the configured window [0.5 %, 1.5 %] theta_max."""
+    import numpy as np
+    import torch
+    res = {}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = fn()
+        torch.cuda.synchronize()
+        return o, time.perf_counter() - t0
+
+    log("variants: FP64 solve without locking")
+    o, t = timed(lambda: P.pfe_solve_interval(h, lo, hi, D["solve_block"], D["solve_block"],
+                                              degree=D["solve_degree"], tol=W["tol64"], x0=X0,
+                                              locking=0, vectors_on_device=True))
+    res["fp64_no_locking"] = {"seconds": t, "iterations": o["stats"]["iterations"],
+                              "filter_columns": o["stats"]["filter_columns"],
+                              "n_found": int(o["evals"].size)}
+    log("variants: count estimate")
+    cnt, t = timed(lambda: P.pfe_estimate_count(h, lo, hi, 1000, P.PFE_SMOOTH_JACKSON,
+                                                nsamples=32, seed=13))
+    res["count_estimate"] = {"window_count": int(ev64.size), "estimate": cnt, "degree": 1000,
+                             "probes": 32, "seconds": t}
+    log("variants: Lanczos on the Dirac filter")
+    o, t = timed(lambda: P.pfe_solve_lanczos(h, lo, hi, D["solve_block"], block=32,
+                                             max_basis=224, tol=W["tol64"]))
+    st = o["stats"]
+    res["lanczos_dirac"] = {
+        "block": 32, "max_basis": 224, "phi": 0.8, "degree": st["degree"], "seconds": t,
+        "restart_cycles": st["iterations"], "filter_columns": st["filter_columns"],
+        "n_found": int(o["evals"].size), "max_resid": float(o["resid"].max()),
+        "max_rel_eig_diff_vs_subspace_iteration":
+            float(np.max(np.abs(o["evals"] - ev64) / ev64)) if o["evals"].shape == ev64.shape else None}
+    log("variants: sliced solve of [0.5%, 1.5%] theta_max")
+    o, t = timed(lambda: P.pfe_solve_sliced(h, 0.005 * th, 0.015 * th, 1024, D["solve_block"],
+                                            per_slice=48, tol=W["tol64"], want_vectors=True,
+                                            vectors_on_device=True))
+    V = o["evecs"]
+    G = (V @ V.T.contiguous()).cpu().numpy() if V is not None and V.shape[0] else np.zeros((0, 0))
+    res["sliced_configured_window"] = {
+        "window_frac_theta": [0.005, 0.015], "seconds": t, "n_found": int(o["evals"].size),
+        "n_slices": o["n_slices"], "iterations_total": o["stats"]["iterations"],
+        "filter_steps": o["stats"]["filter_steps"], "max_resid": float(o["resid"].max()),
+        "max_offdiag_overlap": float(np.abs(G - np.eye(G.shape[0])).max()) if G.size else None}
+    return res
+
+
 def copy_calibration() -> int:
     """Device-to-device copy of 2 GiB (reads 2 GiB, writes 2 GiB per copy):
     the scale for FETCH_SIZE / WRITE_SIZE counters and the achievable copy
@@ -183,6 +235,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", action="store_true",
+                    help="also time the solver variants (no locking, count, Lanczos, slicing) "
+                         "on the 1e5-atom instance and add them to the line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 2 GiB device buffer 5 times and print the copy bandwidth "
                          "(the reference for the HBM traffic counters)")
@@ -248,6 +303,7 @@ def main() -> int:
             t = time.perf_counter() - t0
         tts[form] = (t, o)
     ev64, ev32 = tts["fp64"][1]["evals"], tts["fp32_form"][1]["evals"]
+    variants = solver_variants(P, h4, slo, shi, th4, S0, ev64, D, W) if args.variants else None
     V_hf = tts["fp64"][1]["evecs"][: D["hf_count"]].contiguous()
     lam_hf = ev64[: D["hf_count"]]
     c4, e4 = 0.5 * (ub4 + lb4), 0.5 * (ub4 - lb4)
@@ -393,6 +449,8 @@ def main() -> int:
                      "clenshaw_stream_bytes_per_launch": clen,
                      "frac_on_clenshaw_bytes": clen / launch64 / 1e9 / HBM_PEAK_GBS},
     }
+    if variants is not None:
+        out["solver_variants_N1e5"] = variants
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample on the host cores)")
         out["cpu_baseline"] = cpu_baseline(g, (last["lam_lb"], last["lam_ub"]), d)

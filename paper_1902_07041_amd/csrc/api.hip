@@ -635,13 +635,15 @@ Err cholqr2(pfe_handle h, const Small& sm, double* X, int64_t n, int q, int64_t 
 Err rayleigh_ritz(pfe_handle h, const Small& sm, double* X, double* W, int64_t n, int q,
                   int64_t ld, std::vector<double>& theta, std::vector<double>& res,
                   double* t_rr, double* t_res, GemmAcct* ga = nullptr) {
-  const pfe::Bsr A = h->bsr();
+  pfe::Bsr A;
+  const double* vals = nullptr;
+  PFE_TRY(filter_set64(h, q, &A, &vals));   // W = H X walks the filter's tiles for this width
   const bool tg = ga && ga->on;
   const double f2 = 2.0 * (double)n * q * q;
   {
     Timer tm(h, t_rr);
-    PFE_HIP(pfe::cheb_step_f64(A, h->step_vals64(), X, nullptr, nullptr, W, q, ld, 1.0, 0.0,
-                               0.0, 0.0, h->stream));
+    PFE_HIP(pfe::cheb_step_f64(A, vals, X, nullptr, nullptr, W, q, ld, 1.0, 0.0, 0.0, 0.0,
+                               h->stream));
     {
       Timer tg1(h, tg ? &ga->t : nullptr, 1);
       PFE_HIP(pfe::gram_f64(n, q, q, X, ld, W, ld, sm.S, h->wsRed.p, h->stream));

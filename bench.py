@@ -86,8 +86,12 @@ def log(msg: str) -> None:
 
 
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_1902_07041_amd", "csrc", "k_sparse.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the filter kernel's source and of the row orders its tiles are
+    built in (both decide its memory traffic)."""
+    h = hashlib.sha256()
+    for f in ("k_sparse.hip", "reorder.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_1902_07041_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 # the FP64 filter's kernel at the benchmark shape: three-row tiles (one record

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/pfeig.h"
+#include "reorder.h"
 
 namespace pfe {
 
@@ -94,19 +95,6 @@ struct Bsr {
   int64_t span = 0;          // typical long neighbour offset in rows (natural order)
 };
 
-// Processing order of the atom rows in which contiguous ranges are compact in
-// the graph of the (symmetric) pattern: recursive BFS bisection down to
-// ranges of `leaf` rows (split at multiples of R), and inside each leaf
-// groups of R rows sharing many block columns.
-void locality_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int leaf, int R,
-                    std::vector<int32_t>& order);
-// 90th percentile of the row offsets |i - j| of the off-diagonal blocks,
-// leaving out offsets above n/2 (periodic wrap-around); 0 without any.
-int64_t neighbour_span(int64_t n, const int64_t* row_ptr, const int32_t* col_idx);
-// Fraction of the off-diagonal blocks (i, j) whose rows lie more than
-// `window` positions apart in the processing order `order` (nullptr: natural).
-double far_block_fraction(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
-                          const int32_t* order, int64_t window);
 // Host construction of the row tiles of a block-CSR pattern (see Bsr), the
 // rows taken R at a time in `order` (nullptr: natural order); perm[p] is the
 // row-order index of the block at tile-order position p.

@@ -20,7 +20,7 @@
 #include <utility>
 #include <vector>
 
-#include "internal.h"
+#include "reorder.h"
 
 namespace pfe {
 
@@ -151,6 +151,62 @@ void locality_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, i
       next.emplace_back(mid, b);
     }
     ranges.swap(next);
+  }
+}
+
+void window_group_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                        int64_t window, int R, std::vector<int32_t>& order) {
+  order.clear();
+  order.reserve((size_t)std::max<int64_t>(n, 0));
+  R = std::max(R, 1);
+  window = std::max<int64_t>(R, (window + R - 1) / R * R);
+  std::vector<char> taken((size_t)std::max<int64_t>(n, 0), 0);
+  std::vector<int32_t> mark((size_t)std::max<int64_t>(n, 0), -1);   // group stamp of union columns
+  std::vector<int32_t> cand((size_t)std::max<int64_t>(n, 0), -1);   // step stamp of visited candidates
+  std::vector<int32_t> group;
+  int32_t gstamp = 0, cstamp = 0;
+  for (int64_t a = 0; a < n; a += window) {
+    const int64_t b = std::min(n, a + window);
+    int64_t next_free = a;   // rows only ever become taken, so this only moves forward
+    for (int64_t v0 = a; v0 < b; ++v0) {
+      if (taken[v0]) continue;
+      ++gstamp;
+      group.assign(1, (int32_t)v0);
+      taken[v0] = 1;
+      for (int64_t k = row_ptr[v0]; k < row_ptr[v0 + 1]; ++k) mark[col_idx[k]] = gstamp;
+      while ((int)group.size() < R) {
+        ++cstamp;
+        int32_t best = -1;
+        int64_t best_new = 0, best_ov = 0;
+        for (size_t gi = 0; gi < group.size(); ++gi) {
+          const int32_t u = group[gi];
+          for (int64_t k = row_ptr[u]; k < row_ptr[u + 1]; ++k) {
+            const int32_t w = col_idx[k];
+            if (w < a || w >= b || taken[w] || cand[w] == cstamp) continue;
+            cand[w] = cstamp;
+            int64_t ov = 0;
+            for (int64_t kk = row_ptr[w]; kk < row_ptr[w + 1]; ++kk) ov += mark[col_idx[kk]] == gstamp;
+            const int64_t nw = (row_ptr[w + 1] - row_ptr[w]) - ov;
+            if (best < 0 || nw < best_new || (nw == best_new && (ov > best_ov ||
+                                                                 (ov == best_ov && w < best)))) {
+              best = w;
+              best_new = nw;
+              best_ov = ov;
+            }
+          }
+        }
+        if (best < 0) {   // no free neighbour in the window: the next free row
+          next_free = std::max<int64_t>(next_free, v0 + 1);
+          while (next_free < b && taken[next_free]) ++next_free;
+          if (next_free >= b) break;
+          best = (int32_t)next_free;
+        }
+        taken[best] = 1;
+        group.push_back(best);
+        for (int64_t k = row_ptr[best]; k < row_ptr[best + 1]; ++k) mark[col_idx[k]] = gstamp;
+      }
+      order.insert(order.end(), group.begin(), group.end());
+    }
   }
 }
 

@@ -96,3 +96,18 @@ def test_lanczos_host_bookkeeping_sanitized(tmp_path):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "b=8 m=48" in r.stdout and r.stdout.rstrip().endswith("ALL OK")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_tile_row_orders_sanitized(tmp_path):
+    exe = tmp_path / "reorder_check"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-D_GLIBCXX_ASSERTIONS", "-I", CSRC,
+           os.path.join(ROOT, "tests", "reorder_check.cpp"),
+           os.path.join(CSRC, "reorder.cpp"), "-o", str(exe)]
+    subprocess.run(cmd, check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1"))
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "window holes n=2121 W=4096 R=4" in r.stdout and r.stdout.rstrip().endswith("ALL OK")

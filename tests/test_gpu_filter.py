@@ -177,6 +177,38 @@ def test_filter_row_orders(case, numbering, tile_rows, monkeypatch):
         np.testing.assert_array_equal(out[mode][1], out["0"][1])
 
 
+@pytest.mark.parametrize("tile_rows", ["3", "4"])
+def test_filter_window_grouping(case, tile_rows, monkeypatch):
+    """Tiles of three or more rows regroup the natural order inside windows
+    of rows (default, a 64-row window, and none): the same bits in FP64 and
+    FP32 (each row sums its blocks in column order), matching the oracle."""
+    banner(f"apply_filter with regrouped tiles, tile_rows={tile_rows}")
+    monkeypatch.setenv("PFEIG_TILE_ROWS", tile_rows)
+    monkeypatch.setenv("PFEIG_TILE_ROWS_F32", tile_rows)
+    monkeypatch.setenv("PFEIG_ROW_ORDER", "0")
+    f = design(case, 25)
+    X = gaussian_block(case.n, 96, 79)
+    out = {}
+    for w in [None, "64", "0"]:
+        if w is None:
+            monkeypatch.delenv("PFEIG_TILE_WINDOW", raising=False)
+        else:
+            monkeypatch.setenv("PFEIG_TILE_WINDOW", w)
+        h = P.pfe_create(0)
+        try:
+            P.pfe_set_hessian(h, case.g.row_ptr, case.g.col_idx, case.g.blocks, case.g.masses)
+            P.pfe_set_bounds(h, 0.0, case.ub)
+            out[w] = (P.pfe_apply_filter(h, f, X), P.pfe_apply_filter(h, f, X.astype(np.float32)))
+        finally:
+            P.pfe_destroy(h)
+    ref = chebyshev.apply_filter(case.H, f.c, f.e, f.coef, X)
+    assert rel_err(out[None][0], ref) < 1e-12
+    assert rel_err(out[None][1], ref) < 5e-5
+    for w in ["64", "0"]:
+        np.testing.assert_array_equal(out[w][0], out[None][0])
+        np.testing.assert_array_equal(out[w][1], out[None][1])
+
+
 def test_device_inputs_ordered_after_torch_default_stream(case):
     """A block that torch is still computing on its default stream when the
     call is made is read complete: the handle's stream is ordered against it."""

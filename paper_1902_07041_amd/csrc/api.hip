@@ -293,7 +293,7 @@ constexpr double kOrderFarMax = 0.05;
 // 9.06 for four-row tiles, 11.19 -> 10.18 for three-row tiles) while the
 // order of work stays that of the rows.  4e6-atom glass, q = 256: FP32 step
 // 12.41 -> 12.22 ms, FP64 (three-row wide tiles) 27.20 -> 26.87 ms; 1e5
-// atoms, q = 96, FP32: 170.9 -> 161.9 us.  The gain is smaller than the cut
+// atoms, q = 96, FP32: 170.9 -> 161.9 us; 1e6 atoms FP32 at q = 160 2222 -> 2192 us.  The gain is smaller than the cut
 // in gathers because the L2 hit rate falls with it (0.515 -> 0.448 at 4e6
 // atoms).  Two-row tiles keep the natural order.  PFEIG_TILE_WINDOW
 // overrides (0: natural order for every height).

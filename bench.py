@@ -315,6 +315,22 @@ def main() -> int:
     log(f"N=1e5 window of {ev64.size}: FP64 {tts['fp64'][0]:.3f} s, FP32 form "
         f"{tts['fp32_form'][0]:.3f} s")
 
+    # once, before the timed steps: the 4e6-atom pattern's row tiles of both
+    # filters at this block width (built at a filter's first call on a
+    # pattern and kept while it stays), so that every timed step, also with
+    # --warmup 0, is a steady outer iteration
+    with torch.no_grad():
+        sysm.assemble(k0, m0)
+    lbp, ubp, thp = P.pfe_estimate_bounds(h, 30, v0)
+    fp = P.pfe_design_filter(W["win"][0] * thp, W["win"][1] * thp, lbp, ubp, degree=1)
+    for dt in (torch.float64, torch.float32):
+        Xp = X0.to(dt)
+        P.pfe_apply_filter(h, fp, Xp, torch.empty_like(Xp))
+        del Xp
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log("tile sets of both filters built")
+
     def step():
         r = {}
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]

@@ -170,31 +170,47 @@ __global__ __launch_bounds__(256) void k_sddmm_seg_reg(int n_atoms, const int64_
     for (int r = 0; r < 3; ++r)
       ar[mm][r] = (mm < m && act) ? wm * A[mm * a_stride + (int64_t)(3 * row + r) * ld + c] : 0.0;
   }
-  for (int64_t k = row_ptr[row]; k < row_ptr[row + 1]; ++k) {
-    const int j = col_idx[k];
+  // Software-pipelined over the row's blocks: the next block's rows of t_m
+  // and its current value in G are requested before this block's sums are
+  // reduced and stored, so the reductions overlap those loads and a store
+  // is never older than the loads the next wait is for.
+  const int64_t k0 = row_ptr[row], k1 = row_ptr[row + 1];
+  double tr[MM][3];
+  double gnext = 0.0;
+  auto fetch = [&](int64_t kk) {
+    const int j = col_idx[kk];
+#pragma unroll
+    for (int mm = 0; mm < MM; ++mm) {
+      const double* tm = T + mm * t_stride + (int64_t)(3 * j) * ld + c;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) tr[mm][r] = (mm < m && act) ? tm[(int64_t)r * ld] : 0.0;
+    }
+    gnext = lane < 9 ? G[kk * 9 + lane] : 0.0;
+  };
+  if (k0 < k1) fetch(k0);
+  for (int64_t k = k0; k < k1; ++k) {
     double g[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) g[e] = 0.0;
 #pragma unroll
     for (int mm = 0; mm < MM; ++mm) {
       if (mm < m) {
-        const double* tm = T + mm * t_stride + (int64_t)(3 * j) * ld + c;
-        double tr[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) tr[r] = act ? tm[(int64_t)r * ld] : 0.0;
 #pragma unroll
         for (int pa = 0; pa < 3; ++pa)
 #pragma unroll
-          for (int qb = 0; qb < 3; ++qb) g[pa * 3 + qb] += ar[mm][pa] * tr[qb];
+          for (int qb = 0; qb < 3; ++qb) g[pa * 3 + qb] += ar[mm][pa] * tr[mm][qb];
       }
     }
+    const double gk = gnext;
+    if (k + 1 < k1) fetch(k + 1);
+    __builtin_amdgcn_sched_barrier(0);   // the next block's loads go out before the reductions
     double v = 0.0;
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
       const double tot = wave_sum(g[e]);
       if (lane == e) v = tot;
     }
-    if (lane < 9) G[k * 9 + lane] += v;
+    if (lane < 9) G[k * 9 + lane] = gk + v;
   }
 }
 
@@ -378,8 +394,11 @@ hipError_t assemble_springs(int64_t n_atoms, const int64_t* row_ptr, const int32
 
 // Register-resident segment kernels for segments of up to 8, 13 and 16
 // steps (the default stride ceil(sqrt(d)) for d <= 64, 169, 256): the rows
-// of a_m take 6 VGPRs per step, so the smallest fit keeps the most waves
-// (96, 126 and 144 VGPRs: 5, 4 and 3 waves per SIMD).
+// of a_m and the next block's rows of t_m take 12 VGPRs per step, so the
+// smallest fit keeps the most waves (148, 209 and 245 VGPRs: 3, 2 and 2
+// waves per SIMD).  1e5-atom glass, q = 64, d = 150: adjoint 142.6 ->
+// 134.7 ms against the kernel that loaded each block's rows after storing
+// the previous block (4 waves per SIMD), same bits.
 constexpr int kSegRegMax = 16;
 
 hipError_t sddmm_seg_f64(const Bsr& A, int q, int m, const double* a, int64_t a_stride,

@@ -4,8 +4,9 @@
 // used by the Lanczos bounds, mass weighting (eq. intro.2) and validation.
 //
 // Mapping of the fused step: one wavefront per row tile (two atom rows, six
-// matrix rows, for FP64; three atom rows for the FP32 filter; one atom row
-// when tiles are off).  Lane l owns NP column
+// matrix rows, for FP64, three for FP64 blocks wider than 192 columns; three
+// atom rows for the FP32 filter, four above 192 columns; one atom row when
+// tiles are off).  Lane l owns NP column
 // chunks of VW contiguous elements, chunk = l + 64 p, so a neighbour's three
 // rows of T_in (3 q contiguous elements) are read by coalesced 8-32 byte
 // vector loads.  A tile's records (column, row mask) arrive with one vector

@@ -329,23 +329,15 @@ constexpr int kMaxRefineApps = 16;
 // caller leaves refine_sweeps at 0.
 constexpr int kSliceRefineSweeps = 8;
 
-// Algorithmic HBM bytes of one filter application of degree d >= 1 (d
-// launches): every launch reads the matrix values, column indices and row
-// pointers once.  Running-sum form (sum_form, d >= 2): 2 multivector
-// streams in the first launch (X gathered, t_1 written), 3 after (t_{k-1}
-// gathered once, t_{k-2} read, t_k written), plus the sum written on every
-// sum step and read on all but the first.  Clenshaw form: 2 in the first
-// launch (X gathered and X), 3 in the second (b_{k+2} = 0 is not read) and
-// 4 after (b_{k+1} gathered once, b_{k+2} and X read, b_k written).
-double filter_bytes(int64_t n_atoms, int64_t nnzb, int q, int elem, int d, bool sum_form) {
+// Algorithmic HBM bytes of one filter application of degree d >= 1 by the
+// Clenshaw recurrence (d launches): every launch reads the matrix values,
+// column indices and row pointers once; the multivector streams are 2 in the
+// first launch (X gathered and X), 3 in the second (b_{k+2} = 0 is not read)
+// and 4 after (b_{k+1} gathered once, b_{k+2} and X read, b_k written).
+double filter_bytes(int64_t n_atoms, int64_t nnzb, int q, int elem, int d) {
   if (d < 1) return 0.0;
   const double mat = (double)nnzb * (9.0 * elem + 4.0) + 8.0 * (n_atoms + 1);
   const double vec = 3.0 * n_atoms * q * elem;
-  if (sum_form && d >= 2) {
-    int nsum = 0;
-    for (int k = 2; k <= d; ++k) nsum += (k % 3 == 2 || k == d) ? 1 : 0;
-    return d * mat + (2.0 + 3.0 * (d - 1) + (2.0 * nsum - 1.0)) * vec;
-  }
   return d * mat + (4.0 * d - 3.0) * vec;
 }
 
@@ -372,67 +364,6 @@ struct Timer {
 };
 
 // ---------------------------------------------------------------- filter
-// Y = p(A) X, A = a1 H + b1 I = sum_k g_k T_k(A) X by the three-term
-// recurrence of Algorithm 2, t_0 = X, t_1 = A X, t_{k+1} = 2 A t_k - t_{k-1},
-// with the running sum Y updated only on every third step: step k (which
-// holds t_{k-2} as prev, t_{k-1} among its gathers and t_k as its output)
-// adds g_{k-2} t_{k-2} + g_{k-1} t_{k-1} + g_k t_k for k = 2, 5, 8, ... and
-// the terms still missing on the last step.  Two steps in three then read
-// no X and no sum, and the third reads and writes the sum: 4e6-atom glass,
-// q = 256: 26.48 -> 25.69 ms per FP64 step and 12.28 -> 11.96 ms per FP32
-// step against the Clenshaw form below (1e5 atoms, q = 96: 273 -> 263 and
-// 166 -> 155 us).  The FP64 filters use it; the FP32 filter keeps the
-// Clenshaw form, whose rounding error in FP32 measured 25-30 % smaller
-// (relative error per column against FP64 at degree 400 on the 1e5-atom
-// glass: 8.2e-6 against 1.1e-5), which keeps the FP32 plateau, and so the
-// FP64 sweep that follows it, as it was.  X is read only; the result lands
-// in P, Q and S are scratch (P, Q, S, X distinct).  d launches; needs row
-// tiles and d >= 2, else run_filter below takes the Clenshaw form.
-template <typename T>
-Err run_filter_sum(pfe_handle h, const pfe::Bsr& A, const T* vals, const double* g, int d,
-                   double a1, double b1, const T* X, T* P, T* Q, T* S, int q, int64_t ld) {
-  auto step = [&](const T* tin, const T* prev, T* out, double al, double be, double de, bool sum,
-                  double y0, double y1, double y2, int yfirst) -> hipError_t {
-    if (!sum) {
-      if constexpr (sizeof(T) == 8)
-        return pfe::cheb_step_f64(A, (const double*)vals, (const double*)tin,
-                                  (const double*)prev, nullptr, (double*)out, q, ld, al, be, de,
-                                  0.0, h->stream);
-      else
-        return pfe::cheb_step_f32(A, (const float*)vals, (const float*)tin, (const float*)prev,
-                                  nullptr, (float*)out, q, ld, (float)al, (float)be, (float)de,
-                                  0.0f, h->stream);
-    }
-    if constexpr (sizeof(T) == 8)
-      return pfe::cheb_sum_step_f64(A, (const double*)vals, (const double*)tin,
-                                    (const double*)prev, (double*)out, q, ld, al, be, de,
-                                    (double*)P, y0, y1, y2, yfirst, h->stream);
-    else
-      return hipErrorInvalidValue;   // the FP32 filter keeps the Clenshaw form
-  };
-  PFE_HIP(step(X, nullptr, Q, a1, b1, 0.0, false, 0.0, 0.0, 0.0, 0));   // t_1 = A X
-  const T* tprev = X;   // t_{k-2}
-  T* tcur = Q;          // t_{k-1}
-  int covered = -1;     // terms 0..covered are in the sum
-  for (int k = 2; k <= d; ++k) {
-    // t_k overwrites t_{k-2} (read as prev by this same step, row by row);
-    // t_2 goes to S, X being read only
-    T* out = k == 2 ? S : const_cast<T*>(tprev);
-    const bool sum = k % 3 == 2 || k == d;
-    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-    if (sum) {
-      if (covered < k - 2) y0 = g[k - 2];
-      if (covered < k - 1) y1 = g[k - 1];
-      y2 = g[k];
-    }
-    PFE_HIP(step(tcur, tprev, out, 2.0 * a1, 2.0 * b1, -1.0, sum, y0, y1, y2, covered < 0 ? 1 : 0));
-    if (sum) covered = k;
-    tprev = tcur;
-    tcur = out;
-  }
-  return pfe::ok();
-}
-
 // Y = p(A) X, A = a1 H + b1 I, by Clenshaw's backward recurrence for a
 // Chebyshev series: b_{d+1} = b_{d+2} = 0, b_k = g_k X + 2 A b_{k+1} - b_{k+2}
 // (k = d..1), Y = g_0 X + A b_1 - b_2.  It evaluates the same polynomial as
@@ -440,18 +371,12 @@ Err run_filter_sum(pfe_handle h, const pfe::Bsr& A, const T* vals, const double*
 // step (no running sum to read and write).  b_d = g_d X is never stored: it
 // is folded into the first launch and into the X coefficient of the second.
 // X is read only; the result lands in P, Q is scratch (P, Q, X distinct).
-// d launches for d >= 1.  With a second scratch multivector S the filter
-// takes the running-sum form above when it can.
+// d launches for d >= 1.
 template <typename T>
 Err run_filter(pfe_handle h, const T* vals, const double* g, int d, double a1, double b1,
                const T* X, T* P, T* Q, int q, int64_t ld, int64_t* steps,
-               const pfe::Bsr* over = nullptr, T* S = nullptr) {
+               const pfe::Bsr* over = nullptr) {
   const pfe::Bsr A = over ? *over : (sizeof(T) == 4 ? h->bsr32() : h->bsr());
-  if (sizeof(T) == 8 && S && d >= 2 && A.tile_rows >= 2 && A.tile_ptr) {
-    PFE_TRY(run_filter_sum<T>(h, A, vals, g, d, a1, b1, X, P, Q, S, q, ld));
-    if (steps) *steps += d;
-    return pfe::ok();
-  }
   auto step = [&](const T* tin, const T* prev, T* out, double al, double be, double de,
                   double ze) -> hipError_t {
     if constexpr (sizeof(T) == 8)
@@ -498,9 +423,8 @@ Err run_filter(pfe_handle h, const T* vals, const double* g, int d, double a1, d
 template <typename T>
 Err run_filter(pfe_handle h, const T* vals, const std::vector<double>& g, double a1, double b1,
                const T* X, T* P, T* Q, int q, int64_t ld, int64_t* steps,
-               const pfe::Bsr* over = nullptr, T* S = nullptr) {
-  return run_filter<T>(h, vals, g.data(), (int)g.size() - 1, a1, b1, X, P, Q, q, ld, steps, over,
-                       S);
+               const pfe::Bsr* over = nullptr) {
+  return run_filter<T>(h, vals, g.data(), (int)g.size() - 1, a1, b1, X, P, Q, q, ld, steps, over);
 }
 
 // The pattern and block values an FP64 filter on blocks `width` columns wide
@@ -1263,7 +1187,6 @@ static Err apply_impl(pfe_handle h, const pfe_filter* f, int nvec, const void* X
   const size_t mv = (size_t)n * ld * elem;
   std::vector<double> coef(f->coef, f->coef + f->degree + 1);
   PFE_HIP(h->wsA.ensure(mv));
-  if (precision == PFE_FP64) PFE_HIP(h->wsB.ensure(mv));   // the running-sum form's second scratch
   if (!dev) {
     PFE_HIP(h->wsC.ensure(mv));
     PFE_HIP(h->wsD.ensure(mv));
@@ -1280,8 +1203,7 @@ static Err apply_impl(pfe_handle h, const pfe_filter* f, int nvec, const void* X
     const double* v64 = nullptr;
     PFE_TRY(filter_set64(h, nvec, &A64, &v64));
     PFE_TRY(run_filter<double>(h, v64, coef, 1.0 / f->e, -f->c / f->e, (const double*)Xd,
-                               (double*)Yd, h->wsA.as<double>(), nvec, ld, nullptr, &A64,
-                               h->wsB.as<double>()));
+                               (double*)Yd, h->wsA.as<double>(), nvec, ld, nullptr, &A64));
   } else {
     PFE_TRY(ensure_h32(h, f->c, f->e, nvec));
     PFE_TRY(run_filter<float>(h, h->H32.as<float>(), coef, 1.0, 0.0, (const float*)Xd,
@@ -1365,18 +1287,18 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
   const bool trace = tr_env && tr_env[0] && tr_env[0] != '0';
   const int64_t ld = round_up(q, 8);
   const size_t mv64 = (size_t)n * ld * sizeof(double);
-  // X, W and a 16-byte/element region R: the two FP64 scratch multivectors
-  // of the FP64 filter's running-sum form, or X32, P32, Q32 of the FP32
-  // filter (Clenshaw form).
+  // FP64 form: X, W and one FP64 scratch.  Mixed form: X64, W64 and a
+  // 12-byte/element region holding X32, P32, Q32 (or, for the refinement
+  // sweep, one FP64 scratch).
   PFE_HIP(h->wsA.ensure(mv64));
   PFE_HIP(h->wsB.ensure(mv64));
-  PFE_HIP(h->wsC.ensure((size_t)n * ld * 16));
+  PFE_HIP(h->wsC.ensure(mixed ? (size_t)n * ld * 12 : mv64));
   double* X = h->wsA.as<double>();
   double* W = h->wsB.as<double>();
   char* R = h->wsC.as<char>();
   PFE_HIP(pfe::zero_f64(X, n * ld, h->stream));
   PFE_HIP(pfe::zero_f64(W, n * ld, h->stream));
-  PFE_HIP(pfe::zero_f64((double*)R, (int64_t)n * ld * 2, h->stream));
+  PFE_HIP(pfe::zero_f64((double*)R, (int64_t)(mixed ? n * ld * 12 : mv64) / 8, h->stream));
   Small sm;
   PFE_TRY(alloc_small(h, q, &sm));
   PFE_TRY(ensure_red(h, n, q));
@@ -1469,9 +1391,8 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
         PFE_TRY(filter_set64(h, q, &A64, &v64));
         Timer tm(h, &st.t_filter);
         PFE_TRY(run_filter<double>(h, v64, fd.coef, 1.0 / fd.e, -fd.c / fd.e, Fin, Fout,
-                                   (double*)R, nf, ld, &st.filter_steps, &A64,
-                                   (double*)R + n * ld));
-        st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 8, fd.degree, h->tile_rows >= 2);
+                                   (double*)R, nf, ld, &st.filter_steps, &A64));
+        st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 8, fd.degree);
         if (mixed) st.refine_applications++;
         if (trace && reps > 1) {
           PFE_TRY(sync(h));
@@ -1489,7 +1410,7 @@ static Err solve_impl(pfe_handle h, double lam_lo, double lam_hi, int nev,
       PFE_TRY(run_filter<float>(h, h->H32.as<float>(), fd.coef, 1.0, 0.0, X32, P32, Q32, nf, ld,
                                 &st.filter_steps));
       PFE_HIP(pfe::cast_f32_to_f64(n, nf, P32, ld, Fout, ld, h->stream));
-      st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 4, fd.degree, false);
+      st.filter_bytes += filter_bytes(h->n_atoms, h->nnzb, nf, 4, fd.degree);
     }
     {
       // Filtered columns obey the filter's bound; locked ones were carried

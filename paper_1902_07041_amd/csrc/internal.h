@@ -120,14 +120,6 @@ hipError_t cheb_step_f64(const Bsr& A, const double* vals, const double* tin, co
 hipError_t cheb_step_f32(const Bsr& A, const float* vals, const float* tin, const float* prev,
                          const float* add, float* out, int q, int64_t ld, float alpha, float beta,
                          float delta, float zeta, hipStream_t s);
-// The same step in FP64 (no add stream) that also updates a running sum:
-//   ysum_i <- (yfirst ? 0 : ysum_i) + y0 prev_i + y1 tin_i + y2 out_i.
-// ysum must not alias tin, prev or out.  Needs row tiles (A.tile_rows >= 2;
-// hipErrorInvalidValue otherwise).
-hipError_t cheb_sum_step_f64(const Bsr& A, const double* vals, const double* tin,
-                             const double* prev, double* out, int q, int64_t ld, double alpha,
-                             double beta, double delta, double* ysum, double y0, double y1,
-                             double y2, int yfirst, hipStream_t s);
 
 // y = H x for a single vector (q = 1), FP64.
 hipError_t spmv_f64(const Bsr& A, const double* vals, const double* x, double* y, hipStream_t s);

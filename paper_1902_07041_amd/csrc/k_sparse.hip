@@ -205,20 +205,13 @@ __global__ __launch_bounds__(256) void k_cheb_step(
 // column), so the tile ends with stores only instead of two more serial
 // memory round trips.  alpha == 0 (no matrix term): acc = cb tin + cd prev
 // + cz add at tile start, no record loop, out = acc.
-//
-// With YS (a running-sum step of the forward recurrence of Algorithm 2) the
-// step also updates the sum Y = sum_k g_k t_k from the three vectors it
-// holds anyway: Y <- Y + y0 prev + y1 tin_i + y2 out (Y read at tile start
-// with prev unless yfirst, tin_i on the record of row i's own column, the
-// new Y stored with out), so the sum costs one read and one write on the
-// steps that carry it and nothing on the others.
-template <typename T, int VW, int NP, int U, int R, bool YS>
+template <typename T, int VW, int NP, int U, int R>
 __global__ __launch_bounds__(256) void k_cheb_tile(
     int n_atoms, int n_tiles, const int64_t* __restrict__ tile_ptr,
     const int64_t* __restrict__ tile_vptr, const int2* __restrict__ tile_cm,
     const int32_t* __restrict__ tile_row, const T* __restrict__ vals,
     const T* __restrict__ tin, const T* prev, const T* add, T* out, int q, int pass_w,
-    int64_t ld, T alpha, T cb, T cd, T cz, int chunk, T* ysum, T y0, T y1, T y2, int yfirst) {
+    int64_t ld, T alpha, T cb, T cd, T cz, int chunk) {
   static_assert(64 % U == 0, "a record batch must not straddle two 64-record windows");
   using vt = typename VT<T, VW>::type;
   const int lb = map_block(blockIdx.x, chunk);
@@ -303,34 +296,6 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[r][a][p] = c1 * v1[r][a][p];
   };
-  vt yv[R][3][NP];   // the running sum's rows (YS)
-  if constexpr (YS) {   // acc = cd prev, Y = Y_old + y0 prev, both requested at tile start
-    const bool use_prev = cd != T(0) || y0 != T(0);
-    vt pv[R][3][NP], yo[R][3][NP];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int64_t o = rb[r] + boff[a][p];
-          pv[r][a][p] = use_prev ? ld_nt(reinterpret_cast<const vt*>(
-                                       reinterpret_cast<const char*>(prev) + o))
-                                 : vt(0);
-          yo[r][a][p] = yfirst ? vt(0)
-                               : ld_nt(reinterpret_cast<const vt*>(
-                                     reinterpret_cast<const char*>(ysum) + o));
-        }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          acc[r][a][p] = cd * pv[r][a][p];
-          yv[r][a][p] = yo[r][a][p] + y0 * pv[r][a][p];
-        }
-  } else
   if (!mat && cb != T(0)) {   // no matrix term: tin enters here, not through the loop
     if (cd != T(0)) {
       start2(tin, cb, prev, cd);
@@ -450,14 +415,6 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
 #pragma unroll
               for (int a = 0; a < 3; ++a) acc[r][a][p] += cb * x[u][a][p];
           }
-          if constexpr (YS) {   // row r's own column: t_k of the sum
-            if ((m >> (R + r)) & 1) {
-#pragma unroll
-              for (int p = 0; p < NP; ++p)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) yv[r][a][p] += y1 * x[u][a][p];
-            }
-          }
         }
       }
     }
@@ -477,10 +434,6 @@ __global__ __launch_bounds__(256) void k_cheb_tile(
           st_nt(o, reinterpret_cast<vt*>(op + boff[a][p]));
         else
           *reinterpret_cast<vt*>(op + boff[a][p]) = o;
-        if constexpr (YS) {
-          char* yp = reinterpret_cast<char*>(ysum) + (int64_t)rows[r] * ld3 * (int64_t)sizeof(T);
-          st_nt(yv[r][a][p] + y2 * o, reinterpret_cast<vt*>(yp + boff[a][p]));
-        }
       }
     }
   }
@@ -512,8 +465,7 @@ int chunk_override() { return env_int("PFEIG_CHEB_CHUNK", -1); }
 template <typename T, int VW, int NP>
 hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, const T* add,
                        T* out, int q, int pass_w, int64_t ld, T alpha, T beta, T delta,
-                       T zeta, hipStream_t s, T* ysum = nullptr, T y0 = 0, T y1 = 0, T y2 = 0,
-                       int yfirst = 0) {
+                       T zeta, hipStream_t s) {
   const int R = (A.tile_rows >= 2 && A.tile_ptr) ? A.tile_rows : 1;   // vals in tile order
   if (R >= 2 && (3 * ld) * (int64_t)sizeof(T) > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
   const int64_t units = (R >= 2) ? A.n_tiles : A.n_atoms;   // one wave per unit
@@ -546,49 +498,21 @@ hipError_t launch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev,
   // block values (U R 9 doubles) stay within the scalar registers.
   constexpr int U34 = sizeof(T) == 8 ? 1 : kTileUnroll;
   if (R == 2) {
-    if (ysum) {
-      if constexpr (sizeof(T) == 8)   // running-sum steps: the FP64 filter only
-        hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 2, true>), grid, dim3(256), 0, s,
-                           (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                           A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd,
-                           cz, chunk, ysum, y0, y1, y2, yfirst);
-      else
-        return hipErrorInvalidValue;
-    } else
-      hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 2, false>), grid, dim3(256), 0, s,
-                         (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                         A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
-                         chunk, (T*)nullptr, T(0), T(0), T(0), 0);
+    hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, kTileUnroll, 2>), grid, dim3(256), 0, s,
+                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
+                       A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
+                       chunk);
   } else if (R == 3) {
-    if (ysum) {
-      if constexpr (sizeof(T) == 8)   // running-sum steps: the FP64 filter only
-        hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, U34, 3, true>), grid, dim3(256), 0, s,
-                           (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                           A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd,
-                           cz, chunk, ysum, y0, y1, y2, yfirst);
-      else
-        return hipErrorInvalidValue;
-    } else
-      hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, U34, 3, false>), grid, dim3(256), 0, s,
-                         (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                         A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
-                         chunk, (T*)nullptr, T(0), T(0), T(0), 0);
+    hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, U34, 3>), grid, dim3(256), 0, s,
+                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
+                       A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
+                       chunk);
   } else if (R == 4) {
-    if (ysum) {
-      if constexpr (sizeof(T) == 8)   // running-sum steps: the FP64 filter only
-        hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, U34, 4, true>), grid, dim3(256), 0, s,
-                           (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                           A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd,
-                           cz, chunk, ysum, y0, y1, y2, yfirst);
-      else
-        return hipErrorInvalidValue;
-    } else
-      hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, U34, 4, false>), grid, dim3(256), 0, s,
-                         (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
-                         A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
-                         chunk, (T*)nullptr, T(0), T(0), T(0), 0);
+    hipLaunchKernelGGL((k_cheb_tile<T, VW, NP, U34, 4>), grid, dim3(256), 0, s,
+                       (int)A.n_atoms, (int)A.n_tiles, A.tile_ptr, A.tile_vptr, A.tile_cm,
+                       A.tile_row, vals, tin, prev, add, out, q, pass_w, ld, alpha, cb, cd, cz,
+                       chunk);
   } else {
-    if (ysum) return hipErrorInvalidValue;   // running-sum steps need row tiles
     hipLaunchKernelGGL((k_cheb_step<T, VW, NP, kUnroll>), grid, dim3(256), 0, s, (int)A.n_atoms,
                        A.row_ptr, A.col_idx, vals, tin, prev, add, out, q, pass_w, ld, alpha,
                        beta, delta, zeta, chunk);
@@ -606,8 +530,7 @@ bool aligned(const void* p, int bytes) {
 template <typename T, int MAXVW>
 hipError_t dispatch_cheb(const Bsr& A, const T* vals, const T* tin, const T* prev, const T* add,
                          T* out, int q, int64_t ld, T alpha, T beta, T delta, T zeta,
-                         hipStream_t s, T* ysum = nullptr, T y0 = 0, T y1 = 0, T y2 = 0,
-                         int yfirst = 0) {
+                         hipStream_t s) {
   if (A.n_atoms == 0 || q == 0) return hipSuccess;
   // smallest vector width that covers q with one 64-lane pass, if the
   // layout allows it; otherwise the widest that does
@@ -620,7 +543,7 @@ hipError_t dispatch_cheb(const Bsr& A, const T* vals, const T* tin, const T* pre
   auto fits = [&](int v) {
     const int bytes = v * (int)sizeof(T);
     return q % v == 0 && ld % v == 0 && aligned<T>(tin, bytes) && aligned<T>(prev, bytes) &&
-           aligned<T>(out, bytes) && aligned<T>(add, bytes) && aligned<T>(ysum, bytes);
+           aligned<T>(out, bytes) && aligned<T>(add, bytes);
   };
   int vw = want;
   while (vw > 1 && !fits(vw)) vw /= 2;
@@ -649,7 +572,7 @@ hipError_t dispatch_cheb(const Bsr& A, const T* vals, const T* tin, const T* pre
 #define PFE_CHEB_CASE(VW_, NP_)                                                               \
   if (vw == VW_ && np == NP_)                                                                 \
     return launch_cheb<T, VW_, NP_>(A, vals, tin, prev, add, out, q, pass_w, ld, alpha, beta, \
-                                    delta, zeta, s, ysum, y0, y1, y2, yfirst);
+                                    delta, zeta, s);
   PFE_CHEB_CASE(1, 1)
   PFE_CHEB_CASE(1, 2)
   PFE_CHEB_CASE(1, 4)
@@ -776,13 +699,6 @@ inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
-hipError_t cheb_sum_step_f64(const Bsr& A, const double* vals, const double* tin,
-                             const double* prev, double* out, int q, int64_t ld, double alpha,
-                             double beta, double delta, double* ysum, double y0, double y1,
-                             double y2, int yfirst, hipStream_t s) {
-  return dispatch_cheb<double, 4>(A, vals, tin, prev, nullptr, out, q, ld, alpha, beta, delta,
-                                  0.0, s, ysum, y0, y1, y2, yfirst);
-}
 hipError_t cheb_step_f64(const Bsr& A, const double* vals, const double* tin, const double* prev,
                          const double* add, double* out, int q, int64_t ld, double alpha,
                          double beta, double delta, double zeta, hipStream_t s) {
